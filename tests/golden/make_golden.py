@@ -1,0 +1,67 @@
+"""Writes the stored fixtures under tests/golden/.
+
+Inputs come from `synth` (seeded); every expected value comes from `oracle`
+only. Run from the repository root:
+
+    python tests/golden/make_golden.py digests
+    python tests/golden/make_golden.py c1 [n_sample]
+    python tests/golden/make_golden.py c3 [n_sample]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def digests():
+    with open(os.path.join(HERE, "c0_digest.txt"), "w") as f:
+        f.write(synth.gen(0).digest() + "  synth.gen(0)\n")
+
+
+def sampled(config_id, n_sample):
+    """Oracle logL at an evenly spaced sample of the config's theta batch."""
+    import oracle
+    orc = oracle.get()
+    inst = synth.gen(config_id)
+    B = inst.theta.shape[0]
+    idx = np.unique(np.linspace(0, B - 1, n_sample).round().astype(int))
+    t0 = time.time()
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    t1 = time.time()
+    logL, info, terms = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var,
+                                    inst.bin_scale, inst.theta[idx], terms=True)
+    t2 = time.time()
+    out = {
+        "config": config_id,
+        "digest": inst.digest(),
+        "m": inst.m, "n": inst.n, "n_k": inst.n_k, "B": B,
+        "c": c, "K0": K0,
+        "dbar_head": [[float(z.real), float(z.imag)] for z in dbar[:8]],
+        "A_samples": [[int(j), int(k), float(A[j, k].real), float(A[j, k].imag)]
+                      for j, k in [(0, 0), (1, 0), (5, 3), (inst.n - 1, 0), (inst.n - 1, inst.n - 1),
+                                   (inst.n // 2, inst.n // 3), (inst.n - 2, inst.n // 2)]],
+        "index": idx.tolist(),
+        "logL": logL.tolist(),
+        "info": info.tolist(),
+        "terms": terms.tolist(),
+        "oracle_seconds": {"precompute": t1 - t0, "loglike": t2 - t1},
+    }
+    with open(os.path.join(HERE, f"c{config_id}_oracle_sample.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1]
+    if what == "digests":
+        digests()
+    else:
+        sampled(int(what[1:]), int(sys.argv[2]) if len(sys.argv) > 2 else 8)
