@@ -1,0 +1,146 @@
+/*
+ * eor.h - C ABI of the batched FP64 marginal likelihood of the 21-cm power
+ * spectrum for one AMD MI355X (gfx950).
+ *
+ * The problem (Summary and Statement of need; eq. 1 for the k-bins): data
+ * d = T a + e with a dense complex instrument/model matrix T (m x n) over the
+ * joint EoR + foreground coefficients, a ~ CN(0, Phi(theta)), e ~ CN(0, N),
+ * N = diag(sigma^2). The sky coefficients are marginalised analytically, so
+ * only theta, the log10 power per spherical k-bin, is sampled. Per theta:
+ *
+ *   Phi_jj  = s_b 10^theta_b  if coefficient j lies in k-bin b (eq. 1: every
+ *             voxel of a shell shares the bin's power), else a fixed variance
+ *   Sigma   = A + Phi^{-1},  A = T^H N^{-1} T,  dbar = T^H N^{-1} d
+ *   logL    = -m ln(pi) - sum ln sigma_i^2 - ln det Phi - ln det Sigma
+ *             - (d^H N^{-1} d - dbar^H Sigma^{-1} dbar)
+ *
+ * which equals ln CN(d; 0, N + T Phi T^H) exactly (Woodbury identity and
+ * matrix-determinant lemma). Complex Gaussians are circular: E[a a^H] = Phi,
+ * E[e e^H] = N, with no factors of 1/2.
+ *
+ * Conventions of every entry point:
+ *  - Complex numbers are complex128, interleaved (re, im) doubles.
+ *  - "device" pointers are HIP device memory on the context's device;
+ *    "host" pointers are ordinary host memory. The caller owns every buffer it
+ *    passes; the library copies what it keeps.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Calls are
+ *    asynchronous on that stream unless stated; results are valid once the
+ *    stream has reached the call.
+ *  - Argument errors are found before any launch and returned as a negative
+ *    eor_status; eor_last_error() then holds a message (thread-local).
+ *    Numerical failures are reported per theta through `info` and never stop
+ *    the batch. Nothing throws or aborts across the ABI.
+ *  - A context is not thread-safe: use one per host thread.
+ */
+#ifndef EOR_H
+#define EOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eor_ctx eor_ctx;
+typedef struct eor_group eor_group;
+typedef struct eor_surrogate eor_surrogate;
+
+typedef enum {
+    EOR_OK = 0,
+    EOR_ERR_ARG = -1,   /* a bad argument; nothing was launched */
+    EOR_ERR_OOM = -2,   /* device memory could not be allocated */
+    EOR_ERR_HIP = -3,   /* a HIP runtime call failed */
+    EOR_ERR_STATE = -4  /* call out of order (e.g. loglike before precompute) */
+} eor_status;
+
+typedef enum {
+    EOR_PREC_FP64 = 0,    /* A formed in FP64 on FP64 MFMA */
+    EOR_PREC_FP32 = 1,    /* W = T/sigma rounded to complex64, FP32 MFMA, FP32
+                             accumulation per k-chunk, chunks summed in FP64 */
+    EOR_PREC_BF16X3 = 2   /* W split into three bf16 terms, the six leading
+                             cross products on bf16 MFMA with FP32
+                             accumulation per k-chunk, chunks summed in FP64 */
+} eor_precision;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *eor_last_error(void);
+
+/* Version string of the library build. */
+const char *eor_version(void);
+
+/*
+ * Create a context bound to HIP device `device`. *out receives the handle.
+ * Errors: EOR_ERR_ARG (bad device, NULL out), EOR_ERR_HIP.
+ */
+eor_status eor_create(int device, eor_ctx **out);
+
+/* Free the context and all device memory it owns. NULL is a no-op. Waits for
+ * the device to finish the context's work first. */
+void eor_destroy(eor_ctx *ctx);
+
+/*
+ * Once-per-dataset precompute: A = T^H N^{-1} T (stored in FP64 whatever
+ * `prec`), dbar = T^H N^{-1} d, c = d^H N^{-1} d and the constant terms of
+ * logL.
+ *   m, n       rows and columns of T (m >= 1, 1 <= n <= 65536)
+ *   T          device, complex128, row-major m x n with row stride ldT >= n
+ *   noise_var  device [m], sigma_i^2; must be > 0 (not checked on the device)
+ *   d          device complex128 [m]
+ *   n_k        number of k-bins (>= 0)
+ *   bin_of     host int32 [n]: k-bin of each coefficient, or -1 for a
+ *              fixed-variance (foreground) coefficient
+ *   fixed_var  host double [n]: prior variance where bin_of < 0 (> 0);
+ *              other entries are ignored. May be NULL if no bin_of is -1.
+ *   bin_scale  host double [n_k]: s_b > 0, or NULL for all ones
+ *   prec       precision of the A product (eor_precision)
+ * T and d may be freed once the stream has passed this call.
+ * Errors: EOR_ERR_ARG, EOR_ERR_OOM, EOR_ERR_HIP.
+ */
+eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int64_t ldT,
+                          const double *noise_var, const void *d, int32_t n_k,
+                          const int32_t *bin_of, const double *fixed_var,
+                          const double *bin_scale, eor_precision prec, void *stream);
+
+/*
+ * logL for a batch of theta: assemble Sigma(theta), factor it (blocked
+ * complex Cholesky), solve for the quadratic form, reduce the
+ * log-determinants and combine, for every theta of the batch in one launch.
+ *   theta  device double [B x n_k], row-major
+ *   logL   device double [B]
+ *   info   device int32 [B] or NULL: 0 ok; -1 a non-finite theta or prior
+ *          variance; k > 0 the 1-based column whose Cholesky pivot was not
+ *          positive and finite (LAPACK xPOTRF convention). logL = -inf
+ *          whenever info != 0.
+ * B = 0 is a no-op. Per-theta workspace is allocated on first use and kept;
+ * the call is then asynchronous.
+ * Errors: EOR_ERR_ARG, EOR_ERR_STATE (no precompute), EOR_ERR_OOM, EOR_ERR_HIP.
+ */
+eor_status eor_loglike_batch(eor_ctx *ctx, int64_t B, const double *theta, double *logL,
+                             int32_t *info, void *stream);
+
+/*
+ * Same as eor_loglike_batch and also writes, per theta, the terms of logL:
+ *   terms  device double [B x 4]: ln det Sigma, dbar^H Sigma^{-1} dbar,
+ *          ln det Phi, c = d^H N^{-1} d.
+ */
+eor_status eor_loglike_terms(eor_ctx *ctx, int64_t B, const double *theta, double *logL,
+                             int32_t *info, double *terms, void *stream);
+
+/*
+ * Copy the precomputed products out, for checking.
+ *   A_out      device complex128 [n x n] row-major, full Hermitian (ldA >= n)
+ *   dbar_out   device complex128 [n] or NULL
+ *   scalars    host double [2] or NULL: c, K0 = -m ln(pi) - sum ln sigma_i^2
+ *              (synchronises the stream when not NULL)
+ */
+eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *dbar_out,
+                                 double *scalars, void *stream);
+
+/* Problem sizes of a context after eor_precompute: m, n, n_k (any may be NULL). */
+eor_status eor_shape(const eor_ctx *ctx, int64_t *m, int64_t *n, int32_t *n_k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EOR_H */

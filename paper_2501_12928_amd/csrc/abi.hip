@@ -1,0 +1,312 @@
+// C ABI of libeor: argument checking, device memory, and launches.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace eor {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+}  // namespace eor
+
+using eor::Context;
+
+struct eor_ctx {
+    Context c;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+eor_status fail(eor_status st, const std::string &msg) {
+    eor::set_error(msg);
+    return st;
+}
+
+eor_status hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? EOR_ERR_OOM : EOR_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+void free_dev(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_problem(Context &c) {
+    free_dev(c.A);
+    free_dev(c.dbar);
+    free_dev(c.scal);
+    free_dev(c.coef_bin);
+    free_dev(c.coef_inv);
+    free_dev(c.bin_scale);
+    free_dev(c.bin_count);
+    c.ready = false;
+}
+
+void free_work(Context &c) {
+    free_dev(c.Lw);
+    free_dev(c.yw);
+    c.slots = 0;
+}
+
+// Scoped device switch so every call runs on the context's device.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Make sure there is workspace for `want` resident workgroups.
+eor_status ensure_work(Context &c, int64_t want) {
+    if (c.slots >= want) return EOR_OK;
+    free_work(c);
+    const int64_t slot_tiles = eor::n_tiles(c.N);
+    const size_t per_slot = (size_t)slot_tiles * eor::TS2 * sizeof(double2) + (size_t)c.n_pad * sizeof(double2);
+    int64_t slots = want;
+    if (c.work_limit > 0) {
+        const int64_t cap = (int64_t)(c.work_limit / per_slot);
+        if (cap < 1) return fail(EOR_ERR_OOM, "workspace limit is below one theta slot");
+        if (slots > cap) slots = cap;
+    }
+    // Back off if the device cannot hold every slot.
+    while (slots >= 1) {
+        double2 *Lw = nullptr, *yw = nullptr;
+        hipError_t e1 = hipMalloc(&Lw, (size_t)slots * slot_tiles * eor::TS2 * sizeof(double2));
+        hipError_t e2 = e1 == hipSuccess ? hipMalloc(&yw, (size_t)slots * c.n_pad * sizeof(double2)) : e1;
+        if (e1 == hipSuccess && e2 == hipSuccess) {
+            c.Lw = Lw;
+            c.yw = yw;
+            c.slots = slots;
+            c.slot_tiles = slot_tiles;
+            c.slot_y = c.n_pad;
+            return EOR_OK;
+        }
+        if (Lw) (void)hipFree(Lw);
+        if (yw) (void)hipFree(yw);
+        (void)hipGetLastError();
+        if (slots == 1) break;
+        slots = slots / 2;
+    }
+    return fail(EOR_ERR_OOM, "cannot allocate the per-theta workspace");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *eor_last_error(void) { return eor::g_error.c_str(); }
+
+const char *eor_version(void) { return "eor 0.1 gfx950"; }
+
+eor_status eor_create(int device, eor_ctx **out) {
+    if (!out) return fail(EOR_ERR_ARG, "eor_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(EOR_ERR_ARG, "eor_create: no such device");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(EOR_ERR_ARG, std::string("eor_create: built for gfx950, device is ") + prop.gcnArchName);
+    eor_ctx *ctx = new (std::nothrow) eor_ctx;
+    if (!ctx) return fail(EOR_ERR_OOM, "eor_create: host allocation failed");
+    ctx->c.device = device;
+    ctx->c.num_cu = prop.multiProcessorCount;
+    *out = ctx;
+    return EOR_OK;
+}
+
+void eor_destroy(eor_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->c.device);
+    (void)hipDeviceSynchronize();
+    free_problem(ctx->c);
+    free_work(ctx->c);
+    delete ctx;
+}
+
+eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int64_t ldT,
+                          const double *noise_var, const void *d, int32_t n_k, const int32_t *bin_of,
+                          const double *fixed_var, const double *bin_scale, eor_precision prec,
+                          void *stream) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_precompute: ctx is NULL");
+    if (m < 1 || n < 1 || n > 65536) return fail(EOR_ERR_ARG, "eor_precompute: need m >= 1 and 1 <= n <= 65536");
+    if (ldT < n) return fail(EOR_ERR_ARG, "eor_precompute: ldT < n");
+    if (!T || !noise_var || !d || !bin_of) return fail(EOR_ERR_ARG, "eor_precompute: NULL array");
+    if (n_k < 0 || n_k > 4096) return fail(EOR_ERR_ARG, "eor_precompute: need 0 <= n_k <= 4096");
+    if (prec != EOR_PREC_FP64 && prec != EOR_PREC_FP32 && prec != EOR_PREC_BF16X3)
+        return fail(EOR_ERR_ARG, "eor_precompute: unknown precision");
+    // host-side bin map and constants
+    std::vector<int32_t> cnt(n_k > 0 ? n_k : 1, 0);
+    double fixed_logv = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const int32_t b = bin_of[j];
+        if (b < -1 || b >= n_k) return fail(EOR_ERR_ARG, "eor_precompute: bin_of out of range");
+        if (b < 0) {
+            if (!fixed_var || !(fixed_var[j] > 0.0) || !std::isfinite(fixed_var[j]))
+                return fail(EOR_ERR_ARG, "eor_precompute: fixed_var must be finite and > 0 where bin_of < 0");
+            fixed_logv += std::log(fixed_var[j]);
+        } else {
+            cnt[b]++;
+        }
+    }
+    std::vector<double> scale(n_k > 0 ? n_k : 1, 1.0);
+    for (int32_t b = 0; b < n_k; ++b) {
+        if (bin_scale) scale[b] = bin_scale[b];
+        if (!(scale[b] > 0.0) || !std::isfinite(scale[b]))
+            return fail(EOR_ERR_ARG, "eor_precompute: bin_scale must be finite and > 0");
+    }
+
+    Context &c = ctx->c;
+    DeviceGuard g(c.device);
+    hipStream_t s = (hipStream_t)stream;
+    // A previous problem's arrays may still be in use by queued work.
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    free_problem(c);
+    free_work(c);
+    c.m = m;
+    c.n = n;
+    c.N = (n + eor::TS - 1) / eor::TS;
+    c.n_pad = c.N * eor::TS;
+    c.n_k = n_k;
+    c.khost = -(double)m * std::log(kPi);
+    c.fixed_logv = fixed_logv;
+
+    std::vector<int32_t> cbin(c.n_pad, -2);
+    std::vector<double> cinv(c.n_pad, 0.0);
+    for (int64_t j = 0; j < n; ++j) {
+        cbin[j] = bin_of[j];
+        if (bin_of[j] < 0) cinv[j] = 1.0 / fixed_var[j];
+    }
+    const int splits = (int)std::min<int64_t>(64, (m + 255) / 256);
+    double *invvar = nullptr;
+    double2 *partial = nullptr;
+    const size_t a_bytes = (size_t)eor::n_tiles(c.N) * eor::TS2 * sizeof(double2);
+#define EOR_TRY(call, what)                      \
+    do {                                         \
+        hipError_t _e = (call);                  \
+        if (_e != hipSuccess) {                  \
+            free_dev(invvar);                    \
+            free_dev(partial);                   \
+            free_problem(c);                     \
+            return hip_fail(_e, what);           \
+        }                                        \
+    } while (0)
+    EOR_TRY(hipMalloc(&c.A, a_bytes), "hipMalloc A");
+    EOR_TRY(hipMalloc(&c.dbar, c.n_pad * sizeof(double2)), "hipMalloc dbar");
+    EOR_TRY(hipMalloc(&c.scal, 2 * sizeof(double)), "hipMalloc scalars");
+    EOR_TRY(hipMalloc(&c.coef_bin, c.n_pad * sizeof(int32_t)), "hipMalloc bins");
+    EOR_TRY(hipMalloc(&c.coef_inv, c.n_pad * sizeof(double)), "hipMalloc fixed");
+    EOR_TRY(hipMalloc(&c.bin_scale, scale.size() * sizeof(double)), "hipMalloc scales");
+    EOR_TRY(hipMalloc(&c.bin_count, cnt.size() * sizeof(int32_t)), "hipMalloc counts");
+    EOR_TRY(hipMalloc(&invvar, m * sizeof(double)), "hipMalloc invvar");
+    EOR_TRY(hipMalloc(&partial, (size_t)splits * n * sizeof(double2)), "hipMalloc partial");
+    EOR_TRY(hipMemcpyAsync(c.coef_bin, cbin.data(), c.n_pad * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy bins");
+    EOR_TRY(hipMemcpyAsync(c.coef_inv, cinv.data(), c.n_pad * sizeof(double), hipMemcpyHostToDevice, s), "copy fixed");
+    EOR_TRY(hipMemcpyAsync(c.bin_scale, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice, s), "copy scales");
+    EOR_TRY(hipMemcpyAsync(c.bin_count, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy counts");
+
+    const double2 *Td = (const double2 *)T;
+    EOR_TRY(eor::launch_precompute_vectors(c, Td, ldT, noise_var, (const double2 *)d, invvar, partial, splits, s),
+            "precompute vectors");
+    if (prec == EOR_PREC_FP64)
+        EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, invvar, s), "precompute A (fp64)");
+    else if (prec == EOR_PREC_FP32)
+        EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, invvar, s), "precompute A (fp32)");
+    else
+        EOR_TRY(eor::launch_precompute_bf16x3(c, Td, ldT, invvar, s), "precompute A (bf16x3)");
+    // the host vectors above must outlive the async copies; the temporaries too
+    EOR_TRY(hipStreamSynchronize(s), "precompute");
+#undef EOR_TRY
+    free_dev(invvar);
+    free_dev(partial);
+    c.ready = true;
+    return EOR_OK;
+}
+
+static eor_status loglike_impl(eor_ctx *ctx, int64_t B, const double *theta, double *logL, int32_t *info,
+                               double *terms, void *stream) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_loglike_batch: ctx is NULL");
+    Context &c = ctx->c;
+    if (!c.ready) return fail(EOR_ERR_STATE, "eor_loglike_batch: call eor_precompute first");
+    if (B < 0) return fail(EOR_ERR_ARG, "eor_loglike_batch: B < 0");
+    if (B == 0) return EOR_OK;
+    if ((!theta && c.n_k > 0) || !logL) return fail(EOR_ERR_ARG, "eor_loglike_batch: NULL array");
+    DeviceGuard g(c.device);
+    const int64_t resident = (int64_t)eor::like_max_resident_per_cu() * c.num_cu;
+    const int64_t want = B < resident ? B : resident;
+    eor_status st = ensure_work(c, want);
+    if (st != EOR_OK) return st;
+    const int64_t grid = want < c.slots ? want : c.slots;
+    hipError_t e = eor::launch_likelihood(c, B, theta, logL, info, terms, grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "likelihood launch");
+    return EOR_OK;
+}
+
+eor_status eor_loglike_batch(eor_ctx *ctx, int64_t B, const double *theta, double *logL, int32_t *info,
+                             void *stream) {
+    return loglike_impl(ctx, B, theta, logL, info, nullptr, stream);
+}
+
+eor_status eor_loglike_terms(eor_ctx *ctx, int64_t B, const double *theta, double *logL, int32_t *info,
+                             double *terms, void *stream) {
+    if (!terms) return fail(EOR_ERR_ARG, "eor_loglike_terms: terms is NULL");
+    return loglike_impl(ctx, B, theta, logL, info, terms, stream);
+}
+
+eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *dbar_out, double *scalars,
+                                 void *stream) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_export_precompute: ctx is NULL");
+    Context &c = ctx->c;
+    if (!c.ready) return fail(EOR_ERR_STATE, "eor_export_precompute: call eor_precompute first");
+    if (A_out && ldA < c.n) return fail(EOR_ERR_ARG, "eor_export_precompute: ldA < n");
+    DeviceGuard g(c.device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (A_out) {
+        e = eor::launch_export_A(c, (double2 *)A_out, ldA, s);
+        if (e != hipSuccess) return hip_fail(e, "export A");
+    }
+    if (dbar_out) {
+        e = hipMemcpyAsync(dbar_out, c.dbar, c.n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "export dbar");
+    }
+    if (scalars) {
+        double sc[2];
+        e = hipMemcpyAsync(sc, c.scal, sizeof(sc), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "export scalars");
+        scalars[0] = sc[0];
+        scalars[1] = c.khost + sc[1];
+    }
+    return EOR_OK;
+}
+
+eor_status eor_shape(const eor_ctx *ctx, int64_t *m, int64_t *n, int32_t *n_k) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_shape: ctx is NULL");
+    if (!ctx->c.ready) return fail(EOR_ERR_STATE, "eor_shape: call eor_precompute first");
+    if (m) *m = ctx->c.m;
+    if (n) *n = ctx->c.n;
+    if (n_k) *n_k = ctx->c.n_k;
+    return EOR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal declarations shared by the HIP sources of libeor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "eor.h"
+
+namespace eor {
+
+// Side of the square tiles in which A and the Cholesky factor are stored.
+constexpr int TS = 64;
+constexpr int TS2 = TS * TS;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Packed lower-triangular tile storage: tile (i, j), j <= i, starts at
+// tile_index(i, j) * TS2 elements; inside a tile the layout is column-major
+// (element (r, c) at c * TS + r). The tiles of tile-row i are therefore
+// contiguous, and tile-row i restricted to tiles 0..j-1 is a column-major
+// TS x (TS * j) panel with leading dimension TS.
+__host__ __device__ inline int64_t tile_index(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+__host__ __device__ inline int64_t n_tiles(int64_t N) { return N * (N + 1) / 2; }
+
+void set_error(const std::string &msg);
+
+// State behind an eor_ctx handle.
+struct Context {
+    int device = 0;
+    int num_cu = 0;
+    // problem
+    bool ready = false;
+    int64_t m = 0, n = 0, n_pad = 0, N = 0;
+    int32_t n_k = 0;
+    double khost = 0.0;          // -m ln(pi)
+    double fixed_logv = 0.0;     // sum over fixed coefficients of ln v_j
+    double2 *A = nullptr;        // packed lower tiles, n_tiles(N) * TS2
+    double2 *dbar = nullptr;     // [n_pad], zero-padded
+    double *scal = nullptr;      // device [2]: c, -sum ln sigma_i^2
+    int32_t *coef_bin = nullptr; // [n_pad]: bin, -1 fixed, -2 padding
+    double *coef_inv = nullptr;  // [n_pad]: 1/v_j for fixed coefficients, else 0
+    double *bin_scale = nullptr; // [n_k]
+    int32_t *bin_count = nullptr;// [n_k]
+    // per-theta workspace: one slot per resident workgroup
+    double2 *Lw = nullptr;
+    double2 *yw = nullptr;
+    int64_t slots = 0;
+    int64_t slot_tiles = 0;      // tiles per slot
+    int64_t slot_y = 0;          // complex entries of y per slot
+    size_t work_limit = 0;       // bytes; 0 = no limit
+};
+
+// Kernel launchers (precompute.hip, likelihood.hip).
+hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ldT,
+                                  const double *invvar, hipStream_t s);
+hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ldT,
+                                  const double *invvar, hipStream_t s);
+hipError_t launch_precompute_bf16x3(const Context &c, const double2 *T, int64_t ldT,
+                                    const double *invvar, hipStream_t s);
+hipError_t launch_precompute_vectors(const Context &c, const double2 *T, int64_t ldT,
+                                     const double *noise_var, const double2 *d, double *invvar,
+                                     double2 *partial, int splits, hipStream_t s);
+hipError_t launch_export_A(const Context &c, double2 *out, int64_t ldA, hipStream_t s);
+
+struct LikeArgs;
+int like_max_resident_per_cu();
+hipError_t launch_likelihood(const Context &c, int64_t B, const double *theta, double *logL,
+                             int32_t *info, double *terms, int64_t grid, hipStream_t s);
+
+}  // namespace eor

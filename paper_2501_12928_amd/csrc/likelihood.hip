@@ -1,0 +1,407 @@
+// Per-theta marginal likelihood: assemble Sigma = A + Phi^{-1}(theta), factor
+// Sigma = L L^H (blocked complex Cholesky, 64 x 64 tiles), forward-solve
+// y = L^{-1} dbar, reduce ln det Sigma = 2 sum ln L_jj and ||y||^2 = dbar^H
+// Sigma^{-1} dbar, and combine into logL.
+//
+// One workgroup (4 waves) owns one theta at a time and walks the tiles of L
+// left-looking, column by column:
+//
+//   for each tile column j:
+//     diagonal:  S = sum_{k<j} L_jk L_jk^H (MFMA), z = sum_{k<j} L_jk y_k
+//                D = A_jj + diag(Phi^{-1}) - S  -> LDS; Cholesky of D in LDS;
+//                in-place triangular inverse Linv = L_jj^{-1} (kept in LDS);
+//                y_j = Linv (dbar_j - z)
+//     below:     for i > j: X = A_ij - sum_{k<j} L_ik L_jk^H (MFMA)
+//                           L_ij = X Linv^H (MFMA, operand from LDS)
+//
+// Every entry of L is written once and read back only as an MFMA operand,
+// so Sigma is never materialised: A is read once per theta, tile by tile,
+// where the factorisation first needs it. Tile-row i of the packed storage
+// is a column-major 64 x 64j panel (leading dimension 64), so both operands
+// of the update stream with unit stride.
+//
+// The FP64 16x16x4 MFMA takes its A operand as lane l -> A[l%16][l/16], its
+// B operand as lane l -> B[l/16][l%16], and returns D[l/16 + 4r][l%16] in
+// register r. Accumulator layout (wave w owns tile rows 16w..16w+15): for
+// column block cb and register r, lane (q = lane/16, l16 = lane%16) holds
+// element [16w + l16][16cb + q + 4r]. Register r of block cb is then
+// directly the A operand of a 16x16x4 MFMA over columns 16cb + 4r .. +3,
+// which is what the TRSM step consumes without any data movement.
+#include "common.h"
+
+namespace eor {
+
+namespace {
+
+constexpr int NT = 256;  // threads per workgroup (4 waves of 64)
+
+__device__ inline d4 mfma64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Hides a lane-dependent value from loop-invariant code motion, so that the
+// compiler forms tile addresses as one lane offset plus constants where they
+// are used instead of hoisting one register per address out of the loops.
+__device__ inline int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+struct LikeParams {
+    const double2 *A;
+    const double2 *dbar;
+    const int32_t *coef_bin;
+    const double *coef_inv;
+    const double *bin_scale;
+    const int32_t *bin_count;
+    const double *scal;
+    double khost;            // -m ln(pi)
+    double khost_fixed_logv; // sum over fixed coefficients of ln v_j
+    const double *theta;
+    int32_t n_k;
+    int64_t B;
+    int64_t N;
+    double2 *Lw;
+    int64_t slot_tiles;
+    double2 *yw;
+    int64_t slot_y;
+    double *logL;
+    int32_t *info;
+    double *terms;
+};
+
+// Operands of one k-step (4 consecutive columns k0..k0+3 of the panels).
+struct Step {
+    double2 p;     // P[16w + l16][k0 + q]
+    double2 qv[4]; // Q[16cb + l16][k0 + q]
+};
+
+__device__ inline void load_step(Step &s, const double2 *__restrict__ pp, const double2 *__restrict__ qp,
+                                 int64_t k0) {
+    s.p = pp[k0 * TS];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) s.qv[cb] = qp[k0 * TS + 16 * cb];
+}
+
+// acc[i][c] += P[i][k] conj(Q[c][k]):  with p = P, qv = Q,
+//   re: qr pr + qi pi,   im: qr pi - qi pr.
+__device__ inline void mma_step(const Step &s, d4 accR[4], d4 accI[4]) {
+    const double npr = -s.p.x;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        accR[cb] = mfma64(s.qv[cb].x, s.p.x, accR[cb]);
+        accR[cb] = mfma64(s.qv[cb].y, s.p.y, accR[cb]);
+        accI[cb] = mfma64(s.qv[cb].x, s.p.y, accI[cb]);
+        accI[cb] = mfma64(s.qv[cb].y, npr, accI[cb]);
+    }
+}
+
+// S = P Q^H over K columns (K a multiple of 8). With WITHZ, also the
+// partial z[i] = sum_k P[i][k] y[k] of the forward substitution.
+template <bool WITHZ>
+__device__ inline void panel_update(const double2 *__restrict__ P, const double2 *__restrict__ Q,
+                                    const double2 *__restrict__ y, int64_t K, int w, int l16, int q,
+                                    d4 accR[4], d4 accI[4], double &zr, double &zi) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        accR[cb] = d4{0, 0, 0, 0};
+        accI[cb] = d4{0, 0, 0, 0};
+    }
+    if (K == 0) return;
+    const double2 *pp = P + q * TS + 16 * w + l16;
+    const double2 *qp = Q + q * TS + l16;
+    Step cur, nxt;
+    load_step(cur, pp, qp, 0);
+    for (int64_t k0 = 0; k0 < K; k0 += 8) {
+        load_step(nxt, pp, qp, k0 + 4);
+        if (WITHZ) {
+            const double2 yk = y[k0 + q];
+            zr += cur.p.x * yk.x - cur.p.y * yk.y;
+            zi += cur.p.x * yk.y + cur.p.y * yk.x;
+        }
+        mma_step(cur, accR, accI);
+        if (k0 + 8 < K) load_step(cur, pp, qp, k0 + 8);
+        if (WITHZ) {
+            const double2 yk = y[k0 + 4 + q];
+            zr += nxt.p.x * yk.x - nxt.p.y * yk.y;
+            zi += nxt.p.x * yk.y + nxt.p.y * yk.x;
+        }
+        mma_step(nxt, accR, accI);
+    }
+}
+
+__global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
+    __shared__ double2 Dt[TS2];   // diagonal tile: D, then L_jj, then L_jj^{-1}
+    __shared__ double2 wv[TS];    // dbar_j - z, then y_j
+    __shared__ double dg[TS];     // pivots of the current diagonal tile
+    __shared__ double red[TS];    // |y_j|^2 per row
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    const int64_t N = a.N;
+    double2 *L = a.Lw + (int64_t)blockIdx.x * a.slot_tiles * TS2;
+    double2 *yv = a.yw + (int64_t)blockIdx.x * a.slot_y;
+
+    for (int64_t t = blockIdx.x; t < a.B; t += gridDim.x) {
+        const double *th = a.theta + t * a.n_k;
+        // ln det Phi over the binned coefficients, and the theta check.
+        bool ok = true;
+        double ldp = 0.0;
+        for (int b = 0; b < a.n_k; ++b) {
+            const double tb = th[b];
+            if (!isfinite(tb)) ok = false;
+            if (a.bin_count[b] > 0) {
+                const double phi = a.bin_scale[b] * exp10(tb);
+                if (!(phi > 0.0) || !isfinite(phi)) ok = false;
+                ldp += (double)a.bin_count[b] * log(phi);
+            }
+        }
+        if (!ok) {
+            if (tid == 0) {
+                a.logL[t] = -INFINITY;
+                if (a.info) a.info[t] = -1;
+                if (a.terms) {
+                    for (int e = 0; e < 4; ++e) a.terms[4 * t + e] = NAN;
+                }
+            }
+            continue;
+        }
+
+        double logdet = 0.0, quad = 0.0;  // meaningful in thread 0 only
+        int failed = 0;
+
+        for (int64_t j = 0; j < N && !failed; ++j) {
+            __syncthreads();  // previous column's readers of Dt are done
+            const double2 *panel_j = L + tile_index(j, 0) * TS2;
+
+            // ---- diagonal tile --------------------------------------------
+            d4 accR[4], accI[4];
+            double zr = 0.0, zi = 0.0;
+            panel_update<true>(panel_j, panel_j, yv, j * TS, w, l16, q, accR, accI, zr, zi);
+            {
+                const double2 *Ajj = a.A + tile_index(j, j) * TS2;
+                const int lo = opaque(q * TS + 16 * w + l16);  // [16w + l16][q], column-major
+                const int dq = opaque(l16 - q);                // row == col iff cb == w, 4r == dq
+                const int row = 16 * w + l16;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int off = lo + (16 * cb + 4 * r) * TS;
+                        double2 v = Ajj[off];
+                        v.x -= accR[cb][r];
+                        v.y -= accI[cb][r];
+                        if (cb == w && dq == 4 * r) {
+                            const int64_t g = j * TS + row;
+                            const int32_t b = a.coef_bin[g];
+                            const double ip = b >= 0 ? 1.0 / (a.bin_scale[b] * exp10(th[b])) : a.coef_inv[g];
+                            v.x += ip;
+                        }
+                        Dt[off] = v;
+                    }
+                }
+                // reduce z over the four lane groups sharing a row
+                zr += __shfl_xor(zr, 16);
+                zi += __shfl_xor(zi, 16);
+                zr += __shfl_xor(zr, 32);
+                zi += __shfl_xor(zi, 32);
+                if (q == 0) {
+                    const double2 db = a.dbar[j * TS + row];
+                    wv[row] = make_double2(db.x - zr, db.y - zi);
+                }
+            }
+
+            // ---- Cholesky of the diagonal tile in LDS (right-looking) -------
+            // Column c is left unscaled during the sweep; the update uses
+            // D[r][s] -= D[r][c] conj(D[s][c]) / D[c][c].
+            {
+                const int r = tid & 63, qq = tid >> 6;
+                for (int c = 0; c < TS; ++c) {
+                    __syncthreads();
+                    const double dcc = Dt[c * TS + c].x;
+                    if (!(dcc > 0.0) || !isfinite(dcc)) {
+                        failed = (int)(j * TS + c + 1);
+                        break;
+                    }
+                    if (tid == 0) dg[c] = dcc;
+                    if (r > c) {
+                        const double2 lrc = Dt[c * TS + r];
+                        const double sr = lrc.x / dcc, si = lrc.y / dcc;
+                        for (int s = c + 1 + qq; s <= r; s += 4) {
+                            const double2 lsc = Dt[c * TS + s];
+                            // (sr + i si) * conj(lsc)
+                            double2 v = Dt[s * TS + r];
+                            v.x -= sr * lsc.x + si * lsc.y;
+                            v.y -= si * lsc.x - sr * lsc.y;
+                            Dt[s * TS + r] = v;
+                        }
+                    }
+                }
+            }
+            if (failed) break;
+            __syncthreads();
+            // scale: L[c][c] = sqrt(d_c), L[r][c] = D[r][c] / sqrt(d_c); zero the upper part
+            for (int e = tid; e < TS2; e += NT) {
+                const int c = e / TS, r = e % TS;
+                double2 v = Dt[e];
+                if (r == c) {
+                    v = make_double2(sqrt(dg[c]), 0.0);
+                } else if (r > c) {
+                    const double is = 1.0 / sqrt(dg[c]);
+                    v.x *= is;
+                    v.y *= is;
+                } else {
+                    v = make_double2(0.0, 0.0);
+                }
+                Dt[e] = v;
+            }
+            if (tid == 0) {
+                for (int c = 0; c < TS; ++c) logdet += log(dg[c]);
+            }
+            __syncthreads();
+
+            // ---- in-place inverse of the lower-triangular L_jj ---------------
+            // Columns from the last to the first:
+            //   Linv[c][c] = 1 / L[c][c]
+            //   Linv[r][c] = -(sum_{k=c+1..r} Linv[r][k] L[k][c]) / L[c][c],  r > c
+            for (int c = TS - 1; c >= 0; --c) {
+                double2 nv = make_double2(0.0, 0.0);
+                const int r = tid;
+                const double lcc = Dt[c * TS + c].x;
+                if (r < TS && r > c) {
+                    double sr = 0.0, si = 0.0;
+                    for (int k = c + 1; k <= r; ++k) {
+                        const double2 x = Dt[k * TS + r];  // Linv[r][k] (already inverted)
+                        const double2 l = Dt[c * TS + k];  // L[k][c]
+                        sr += x.x * l.x - x.y * l.y;
+                        si += x.x * l.y + x.y * l.x;
+                    }
+                    nv = make_double2(-sr / lcc, -si / lcc);
+                }
+                __syncthreads();
+                if (r < TS && r > c) Dt[c * TS + r] = nv;
+                if (r == c) Dt[c * TS + c] = make_double2(1.0 / lcc, 0.0);
+                __syncthreads();
+            }
+
+            // ---- y_j = Linv (dbar_j - z) ---------------------------------
+            if (tid < TS) {
+                const int r = tid;
+                double sr = 0.0, si = 0.0;
+                for (int c = 0; c <= r; ++c) {
+                    const double2 x = Dt[c * TS + r];
+                    const double2 u = wv[c];
+                    sr += x.x * u.x - x.y * u.y;
+                    si += x.x * u.y + x.y * u.x;
+                }
+                yv[j * TS + r] = make_double2(sr, si);
+                red[r] = sr * sr + si * si;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int r = 0; r < TS; ++r) quad += red[r];
+            }
+
+            // ---- tiles below the diagonal ---------------------------------
+            for (int64_t i = j + 1; i < N; ++i) {
+                const double2 *panel_i = L + tile_index(i, 0) * TS2;
+                panel_update<false>(panel_i, panel_j, nullptr, j * TS, w, l16, q, accR, accI, zr, zi);
+                const double2 *Aij = a.A + tile_index(i, j) * TS2;
+                const int lo = opaque(q * TS + 16 * w + l16);
+                // X = A_ij - S, in the accumulator layout
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double2 v = Aij[lo + (16 * cb + 4 * r) * TS];
+                        accR[cb][r] = v.x - accR[cb][r];
+                        accI[cb][r] = v.y - accI[cb][r];
+                    }
+                }
+                // Y = X Linv^H: Y[i][c'] = sum_c X[i][c] conj(Linv[c'][c]); Linv is
+                // lower triangular, so output block cb2 needs column blocks cb <= cb2.
+                double2 *Lij = L + tile_index(i, j) * TS2;
+                const int lt = opaque(q * TS + l16);            // Linv[l16][q] in LDS
+                const int lw = opaque(l16 * TS + 16 * w + q);   // Y[16w + q][l16] in the tile
+#pragma unroll
+                for (int cb2 = 0; cb2 < 4; ++cb2) {
+                    d4 yR = d4{0, 0, 0, 0}, yI = d4{0, 0, 0, 0};
+#pragma unroll
+                    for (int cb = 0; cb <= cb2; ++cb) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            // Linv[16cb2 + l16][16cb + 4r + q]
+                            const double2 lv = Dt[lt + (16 * cb + 4 * r) * TS + 16 * cb2];
+                            const double xr = accR[cb][r], xi = accI[cb][r];
+                            yR = mfma64(xr, lv.x, yR);
+                            yR = mfma64(xi, lv.y, yR);
+                            yI = mfma64(xi, lv.x, yI);
+                            yI = mfma64(-xr, lv.y, yI);
+                        }
+                    }
+                    // lane holds Y[16w + q + 4r][16cb2 + l16]
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Lij[lw + 16 * cb2 * TS + 4 * r] = make_double2(yR[r], yI[r]);
+                }
+            }
+        }
+
+        if (tid == 0) {
+            const double c = a.scal[0];
+            if (failed) {
+                a.logL[t] = -INFINITY;
+                if (a.info) a.info[t] = failed;
+                if (a.terms) {
+                    for (int e = 0; e < 4; ++e) a.terms[4 * t + e] = NAN;
+                }
+            } else {
+                const double ldphi = ldp + a.khost_fixed_logv;
+                a.logL[t] = (a.khost + a.scal[1]) - ldphi - logdet - (c - quad);
+                if (a.info) a.info[t] = 0;
+                if (a.terms) {
+                    a.terms[4 * t + 0] = logdet;
+                    a.terms[4 * t + 1] = quad;
+                    a.terms[4 * t + 2] = ldphi;
+                    a.terms[4 * t + 3] = c;
+                }
+            }
+        }
+        __syncthreads();  // slot workspace is reused by the next theta
+    }
+}
+
+}  // namespace
+
+int like_max_resident_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, likelihood_kernel, NT, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_likelihood(const Context &c, int64_t B, const double *theta, double *logL,
+                             int32_t *info, double *terms, int64_t grid, hipStream_t s) {
+    LikeParams p;
+    p.A = c.A;
+    p.dbar = c.dbar;
+    p.coef_bin = c.coef_bin;
+    p.coef_inv = c.coef_inv;
+    p.bin_scale = c.bin_scale;
+    p.bin_count = c.bin_count;
+    p.scal = c.scal;
+    p.khost = c.khost;
+    p.khost_fixed_logv = c.fixed_logv;
+    p.theta = theta;
+    p.n_k = c.n_k;
+    p.B = B;
+    p.N = c.N;
+    p.Lw = c.Lw;
+    p.slot_tiles = c.slot_tiles;
+    p.yw = c.yw;
+    p.slot_y = c.slot_y;
+    p.logL = logL;
+    p.info = info;
+    p.terms = terms;
+    hipLaunchKernelGGL(likelihood_kernel, dim3((unsigned)grid), dim3(NT), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace eor

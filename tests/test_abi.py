@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every entry point that the public
+headers declare (no compute calls: no GPU needed)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2501_12928_amd", "libeor.so")
+
+
+def declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(eor_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for required in ("eor_create", "eor_destroy", "eor_precompute", "eor_loglike_batch",
+                     "eor_last_error"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libeor.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libeor.so not built")
+def test_argument_errors_without_gpu():
+    import paper_2501_12928_amd as eor
+    L = eor.lib()
+    assert L.eor_create(0, None) == eor.EOR_ERR_ARG
+    assert b"NULL" in L.eor_last_error()
+    assert L.eor_loglike_batch(None, 1, None, None, None, None) == eor.EOR_ERR_ARG
+    assert L.eor_precompute(None, 1, 1, None, 1, None, None, 0, None, None, None, 0, None) == eor.EOR_ERR_ARG
+    assert eor.version().startswith("eor")
+
+
+def test_product_package_does_not_reference_oracle():
+    """The product path never imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_2501_12928_amd")
+    for path in glob.glob(os.path.join(pkg, "**", "*"), recursive=True):
+        if path.endswith((".py", ".hip", ".h", ".cpp")):
+            text = open(path).read()
+            assert "import oracle" not in text and "from oracle" not in text, path
+            assert "liboracle" not in text and "oracle.c" not in text, path
