@@ -1,0 +1,187 @@
+"""Benchmark: batched FP64 logL evaluations per second at n = 4096.
+
+One step is one pass of the path over one batch: eor_precompute of
+A = T^H N^-1 T, dbar, c from inputs already resident in HBM (T complex128
+20000 x 4096, sigma^2, d), then eor_loglike_batch over B = 512 theta (12
+k-bins): assemble, batched blocked complex Cholesky, forward solve,
+log-determinants and combine. `value` is whole-step throughput
+(B * steps / wall time); the roofline object describes the dominant kernel
+(the per-theta likelihood kernel), timed with HIP events on the stream it runs
+on; the CPU baseline is the FP64 oracle on the host's cores over a bounded
+sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+CONFIG_ID = 3               # 20000 x 4096, 12 bins, B = 512
+KERNEL_SRC = os.path.join(ROOT, "paper_2501_12928_amd", "csrc", "likelihood.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "likelihood_n4096_B512_traffic.json")
+
+
+def flops_per_theta(n: int) -> float:
+    """LAPACK complex convention: Cholesky (4/3) n^3 real flops plus the
+    forward solve 4 n^2 (8 real flops per complex multiply-add)."""
+    return (4.0 / 3.0) * n ** 3 + 4.0 * n ** 2
+
+
+def kernel_digest() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per likelihood launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernel_sha") != kernel_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(inst, n_rows: int = 2000):
+    """The oracle as it stands, on the host's cores, on a bounded sample:
+    precompute over the first n_rows rows of T (scaled to all m rows) and
+    one theta per core at the full n = 4096."""
+    import oracle
+    orc = oracle.get()
+    cores = os.cpu_count() or 1
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    threads = int(env_threads) if env_threads and env_threads.isdigit() else cores
+    threads = max(1, min(threads, cores))
+    rows = min(n_rows, inst.m)
+    t0 = time.perf_counter()
+    A, dbar, c, K0 = orc.precompute(inst.T[:rows], inst.noise_var[:rows], inst.d[:rows], nthreads=threads)
+    t_pre = (time.perf_counter() - t0) * inst.m / rows
+    th = inst.theta[:threads]
+    t0 = time.perf_counter()
+    orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th, nthreads=threads)
+    t_like = time.perf_counter() - t0
+    B = inst.theta.shape[0]
+    step_s = t_pre + t_like * (B / th.shape[0])
+    return {"value": B / step_s, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": (f"precompute over {rows} of {inst.m} rows (time scaled x{inst.m / rows:g}) + "
+                       f"{th.shape[0]} theta at n={inst.n} in parallel (one per thread), scaled to "
+                       f"B={B}; plain C FP64 oracle, OpenMP"),
+            "seconds_measured": round(t_pre * rows / inst.m + t_like, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build targets one GPU: the likelihood batch shards by theta "
+                                   "across GPUs only in design; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        x = torch.ones(nel, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nel * 8, "copy_bytes_written": nel * 8}))
+        return
+
+    import synth
+    import paper_2501_12928_amd as eor
+
+    inst = synth.gen(CONFIG_ID)
+    B, n, m = inst.theta.shape[0], inst.n, inst.m
+    T = torch.from_numpy(inst.T).cuda()
+    nv = torch.from_numpy(inst.noise_var).cuda()
+    d = torch.from_numpy(inst.d).cuda()
+    theta = torch.from_numpy(inst.theta).cuda()
+    logL = torch.empty(B, dtype=torch.float64, device="cuda")
+    info = torch.empty(B, dtype=torch.int32, device="cuda")
+    ctx = eor.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale)
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.loglike_batch(theta, out=logL, info=info)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    like_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+
+    ok = bool((info == 0).all().item()) and bool(torch.isfinite(logL).all().item())
+    if not ok:
+        print(json.dumps({"error": "non-finite logL or nonzero info in the benchmark batch"}))
+        sys.exit(1)
+
+    fl = B * flops_per_theta(n)
+    achieved = fl / (like_ms / 1e3) / 1e12
+    traffic = traffic_per_launch()
+    out = {
+        "metric": "logL evals/s at n=4096 complex FP64, batched",
+        "value": B * args.steps / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"T complex128 {m}x{n} (entries CN(0,1)/sqrt(m)), sigma^2~U(0.5,2), "
+                               f"{inst.n_k} k-bins, {int((inst.bin_of >= 0).sum())} EoR + "
+                               f"{int((inst.bin_of < 0).sum())} foreground coefficients, "
+                               f"B={B} theta~U[-1,3]^{inst.n_k} per call; step = precompute + batch",
+                   "m": m, "n": n, "n_k": inst.n_k, "B": B},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "likelihood_kernel", "launch_ms": like_ms,
+                     "flops_per_launch": fl},
+        "loglike_evals_per_s": B / (like_ms / 1e3),
+        "gated": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst)
+    else:
+        out["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

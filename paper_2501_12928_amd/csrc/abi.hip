@@ -50,6 +50,18 @@ void free_problem(Context &c) {
     free_dev(c.coef_inv);
     free_dev(c.bin_scale);
     free_dev(c.bin_count);
+    free_dev(c.invvar);
+    free_dev(c.partial);
+    if (c.h_bin) (void)hipHostFree(c.h_bin);
+    if (c.h_inv) (void)hipHostFree(c.h_inv);
+    if (c.h_scale) (void)hipHostFree(c.h_scale);
+    if (c.h_count) (void)hipHostFree(c.h_count);
+    c.h_bin = nullptr;
+    c.h_inv = nullptr;
+    c.h_scale = nullptr;
+    c.h_count = nullptr;
+    c.alloc_m = c.alloc_n = 0;
+    c.alloc_k = -1;
     c.ready = false;
 }
 
@@ -177,67 +189,77 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     Context &c = ctx->c;
     DeviceGuard g(c.device);
     hipStream_t s = (hipStream_t)stream;
-    // A previous problem's arrays may still be in use by queued work.
+    // Queued work may still read the previous problem's arrays and the
+    // pinned staging buffers.
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    free_problem(c);
-    free_work(c);
+    const int64_t N = (n + eor::TS - 1) / eor::TS;
+    if (c.alloc_m != m || c.alloc_n != n || c.alloc_k != n_k) {
+        free_problem(c);
+        if (c.N != N) free_work(c);
+    }
+    c.ready = false;
     c.m = m;
     c.n = n;
-    c.N = (n + eor::TS - 1) / eor::TS;
-    c.n_pad = c.N * eor::TS;
+    c.N = N;
+    c.n_pad = N * eor::TS;
     c.n_k = n_k;
     c.khost = -(double)m * std::log(kPi);
     c.fixed_logv = fixed_logv;
 
-    std::vector<int32_t> cbin(c.n_pad, -2);
-    std::vector<double> cinv(c.n_pad, 0.0);
-    for (int64_t j = 0; j < n; ++j) {
-        cbin[j] = bin_of[j];
-        if (bin_of[j] < 0) cinv[j] = 1.0 / fixed_var[j];
-    }
-    const int splits = (int)std::min<int64_t>(64, (m + 255) / 256);
-    double *invvar = nullptr;
-    double2 *partial = nullptr;
-    const size_t a_bytes = (size_t)eor::n_tiles(c.N) * eor::TS2 * sizeof(double2);
+    const int nk1 = n_k > 0 ? n_k : 1;
 #define EOR_TRY(call, what)                      \
     do {                                         \
         hipError_t _e = (call);                  \
         if (_e != hipSuccess) {                  \
-            free_dev(invvar);                    \
-            free_dev(partial);                   \
             free_problem(c);                     \
             return hip_fail(_e, what);           \
         }                                        \
     } while (0)
-    EOR_TRY(hipMalloc(&c.A, a_bytes), "hipMalloc A");
-    EOR_TRY(hipMalloc(&c.dbar, c.n_pad * sizeof(double2)), "hipMalloc dbar");
-    EOR_TRY(hipMalloc(&c.scal, 2 * sizeof(double)), "hipMalloc scalars");
-    EOR_TRY(hipMalloc(&c.coef_bin, c.n_pad * sizeof(int32_t)), "hipMalloc bins");
-    EOR_TRY(hipMalloc(&c.coef_inv, c.n_pad * sizeof(double)), "hipMalloc fixed");
-    EOR_TRY(hipMalloc(&c.bin_scale, scale.size() * sizeof(double)), "hipMalloc scales");
-    EOR_TRY(hipMalloc(&c.bin_count, cnt.size() * sizeof(int32_t)), "hipMalloc counts");
-    EOR_TRY(hipMalloc(&invvar, m * sizeof(double)), "hipMalloc invvar");
-    EOR_TRY(hipMalloc(&partial, (size_t)splits * n * sizeof(double2)), "hipMalloc partial");
-    EOR_TRY(hipMemcpyAsync(c.coef_bin, cbin.data(), c.n_pad * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy bins");
-    EOR_TRY(hipMemcpyAsync(c.coef_inv, cinv.data(), c.n_pad * sizeof(double), hipMemcpyHostToDevice, s), "copy fixed");
-    EOR_TRY(hipMemcpyAsync(c.bin_scale, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice, s), "copy scales");
-    EOR_TRY(hipMemcpyAsync(c.bin_count, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy counts");
+    if (c.alloc_n == 0) {
+        c.splits = (int)std::min<int64_t>(64, (m + 255) / 256);
+        const size_t a_bytes = (size_t)eor::n_tiles(c.N) * eor::TS2 * sizeof(double2);
+        EOR_TRY(hipMalloc(&c.A, a_bytes), "hipMalloc A");
+        EOR_TRY(hipMalloc(&c.dbar, c.n_pad * sizeof(double2)), "hipMalloc dbar");
+        EOR_TRY(hipMalloc(&c.scal, 2 * sizeof(double)), "hipMalloc scalars");
+        EOR_TRY(hipMalloc(&c.coef_bin, c.n_pad * sizeof(int32_t)), "hipMalloc bins");
+        EOR_TRY(hipMalloc(&c.coef_inv, c.n_pad * sizeof(double)), "hipMalloc fixed");
+        EOR_TRY(hipMalloc(&c.bin_scale, nk1 * sizeof(double)), "hipMalloc scales");
+        EOR_TRY(hipMalloc(&c.bin_count, nk1 * sizeof(int32_t)), "hipMalloc counts");
+        EOR_TRY(hipMalloc(&c.invvar, m * sizeof(double)), "hipMalloc invvar");
+        EOR_TRY(hipMalloc(&c.partial, (size_t)c.splits * n * sizeof(double2)), "hipMalloc partial");
+        EOR_TRY(hipHostMalloc((void **)&c.h_bin, c.n_pad * sizeof(int32_t)), "hipHostMalloc");
+        EOR_TRY(hipHostMalloc((void **)&c.h_inv, c.n_pad * sizeof(double)), "hipHostMalloc");
+        EOR_TRY(hipHostMalloc((void **)&c.h_scale, nk1 * sizeof(double)), "hipHostMalloc");
+        EOR_TRY(hipHostMalloc((void **)&c.h_count, nk1 * sizeof(int32_t)), "hipHostMalloc");
+        c.alloc_m = m;
+        c.alloc_n = n;
+        c.alloc_k = n_k;
+    }
+    for (int64_t j = 0; j < c.n_pad; ++j) {
+        c.h_bin[j] = j < n ? bin_of[j] : -2;
+        c.h_inv[j] = (j < n && bin_of[j] < 0) ? 1.0 / fixed_var[j] : 0.0;
+    }
+    for (int b = 0; b < nk1; ++b) {
+        c.h_scale[b] = scale[b];
+        c.h_count[b] = cnt[b];
+    }
+    EOR_TRY(hipMemcpyAsync(c.coef_bin, c.h_bin, c.n_pad * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy bins");
+    EOR_TRY(hipMemcpyAsync(c.coef_inv, c.h_inv, c.n_pad * sizeof(double), hipMemcpyHostToDevice, s), "copy fixed");
+    EOR_TRY(hipMemcpyAsync(c.bin_scale, c.h_scale, nk1 * sizeof(double), hipMemcpyHostToDevice, s), "copy scales");
+    EOR_TRY(hipMemcpyAsync(c.bin_count, c.h_count, nk1 * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy counts");
 
     const double2 *Td = (const double2 *)T;
-    EOR_TRY(eor::launch_precompute_vectors(c, Td, ldT, noise_var, (const double2 *)d, invvar, partial, splits, s),
+    EOR_TRY(eor::launch_precompute_vectors(c, Td, ldT, noise_var, (const double2 *)d, c.invvar, c.partial,
+                                           c.splits, s),
             "precompute vectors");
     if (prec == EOR_PREC_FP64)
-        EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, invvar, s), "precompute A (fp64)");
+        EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, c.invvar, s), "precompute A (fp64)");
     else if (prec == EOR_PREC_FP32)
-        EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, invvar, s), "precompute A (fp32)");
+        EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, c.invvar, s), "precompute A (fp32)");
     else
-        EOR_TRY(eor::launch_precompute_bf16x3(c, Td, ldT, invvar, s), "precompute A (bf16x3)");
-    // the host vectors above must outlive the async copies; the temporaries too
-    EOR_TRY(hipStreamSynchronize(s), "precompute");
+        EOR_TRY(eor::launch_precompute_bf16x3(c, Td, ldT, c.invvar, s), "precompute A (bf16x3)");
 #undef EOR_TRY
-    free_dev(invvar);
-    free_dev(partial);
     c.ready = true;
     return EOR_OK;
 }

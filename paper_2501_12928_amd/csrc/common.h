@@ -45,6 +45,17 @@ struct Context {
     double *coef_inv = nullptr;  // [n_pad]: 1/v_j for fixed coefficients, else 0
     double *bin_scale = nullptr; // [n_k]
     int32_t *bin_count = nullptr;// [n_k]
+    // precompute temporaries, kept so a repeated precompute needs no allocation
+    double *invvar = nullptr;    // [m]
+    double2 *partial = nullptr;  // [splits * n]
+    int splits = 0;
+    // pinned staging of the host-side tables
+    int32_t *h_bin = nullptr;
+    double *h_inv = nullptr;
+    double *h_scale = nullptr;
+    int32_t *h_count = nullptr;
+    int64_t alloc_m = 0, alloc_n = 0;
+    int32_t alloc_k = -1;
     // per-theta workspace: one slot per resident workgroup
     double2 *Lw = nullptr;
     double2 *yw = nullptr;
