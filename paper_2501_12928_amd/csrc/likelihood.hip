@@ -14,6 +14,9 @@
 //     below:     for i > j: X = A_ij - sum_{k<j} L_ik L_jk^H (MFMA)
 //                           L_ij = X Linv^H (MFMA, operand from LDS)
 //
+// The panel updates form each complex product from three real FP64 MFMAs
+// (Gauss's trick) instead of four; the TRSM step keeps four.
+//
 // Every entry of L is written once and read back only as an MFMA operand,
 // so Sigma is never materialised: A is read once per theta, tile by tile,
 // where the factorisation first needs it. Tile-row i of the packed storage
@@ -76,6 +79,10 @@ struct Step {
     double2 qv[4]; // Q[16cb + l16][k0 + q]
 };
 
+// Register prefetch depth of the panel update, in k-steps. The panels come
+// from HBM; four steps in flight cover its latency at two waves per SIMD.
+constexpr int STAGES = 4;
+
 __device__ inline void load_step(Step &s, const double2 *__restrict__ pp, const double2 *__restrict__ qp,
                                  int64_t k0) {
     s.p = pp[k0 * TS];
@@ -83,50 +90,60 @@ __device__ inline void load_step(Step &s, const double2 *__restrict__ pp, const 
     for (int cb = 0; cb < 4; ++cb) s.qv[cb] = qp[k0 * TS + 16 * cb];
 }
 
-// acc[i][c] += P[i][k] conj(Q[c][k]):  with p = P, qv = Q,
-//   re: qr pr + qi pi,   im: qr pi - qi pr.
-__device__ inline void mma_step(const Step &s, d4 accR[4], d4 accI[4]) {
-    const double npr = -s.p.x;
+// acc[i][c] += P[i][k] conj(Q[c][k]) with three real products per complex
+// product (Gauss):  with p = P, q = Q,
+//   T1 = qr pr,  T2 = qi pi,  T3 = (qr - qi)(pr + pi)
+//   re = T1 + T2,  im = T3 - T1 + T2  (= qr pi - qi pr)
+__device__ inline void mma_step(const Step &s, d4 t1[4], d4 t2[4], d4 t3[4]) {
+    const double ps = s.p.x + s.p.y;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-        accR[cb] = mfma64(s.qv[cb].x, s.p.x, accR[cb]);
-        accR[cb] = mfma64(s.qv[cb].y, s.p.y, accR[cb]);
-        accI[cb] = mfma64(s.qv[cb].x, s.p.y, accI[cb]);
-        accI[cb] = mfma64(s.qv[cb].y, npr, accI[cb]);
+        t1[cb] = mfma64(s.qv[cb].x, s.p.x, t1[cb]);
+        t2[cb] = mfma64(s.qv[cb].y, s.p.y, t2[cb]);
+        t3[cb] = mfma64(s.qv[cb].x - s.qv[cb].y, ps, t3[cb]);
     }
 }
 
-// S = P Q^H over K columns (K a multiple of 8). With WITHZ, also the
-// partial z[i] = sum_k P[i][k] y[k] of the forward substitution.
+// S = P Q^H over K columns (K a multiple of 64), returned as (accR, accI).
+// With WITHZ, also the partial z[i] = sum_k P[i][k] y[k] of the forward
+// substitution. The four waves re-align once per 64 columns so that the
+// column panel Q, which all of them read, is fetched from HBM once.
 template <bool WITHZ>
 __device__ inline void panel_update(const double2 *__restrict__ P, const double2 *__restrict__ Q,
                                     const double2 *__restrict__ y, int64_t K, int w, int l16, int q,
                                     d4 accR[4], d4 accI[4], double &zr, double &zi) {
+    d4 t3[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
         accR[cb] = d4{0, 0, 0, 0};
         accI[cb] = d4{0, 0, 0, 0};
+        t3[cb] = d4{0, 0, 0, 0};
     }
     if (K == 0) return;
     const double2 *pp = P + q * TS + 16 * w + l16;
     const double2 *qp = Q + q * TS + l16;
-    Step cur, nxt;
-    load_step(cur, pp, qp, 0);
-    for (int64_t k0 = 0; k0 < K; k0 += 8) {
-        load_step(nxt, pp, qp, k0 + 4);
-        if (WITHZ) {
-            const double2 yk = y[k0 + q];
-            zr += cur.p.x * yk.x - cur.p.y * yk.y;
-            zi += cur.p.x * yk.y + cur.p.y * yk.x;
+    Step buf[STAGES];
+#pragma unroll
+    for (int s0 = 0; s0 < STAGES - 1; ++s0) load_step(buf[s0], pp, qp, 4 * s0);
+    for (int64_t k0 = 0; k0 < K; k0 += 4 * STAGES) {
+        if ((k0 & (TS - 1)) == 0) __syncthreads();
+#pragma unroll
+        for (int u = 0; u < STAGES; ++u) {
+            const int64_t kl = k0 + 4 * (u + STAGES - 1);
+            if (kl < K) load_step(buf[(u + STAGES - 1) % STAGES], pp, qp, kl);
+            if (WITHZ) {
+                const double2 yk = y[k0 + 4 * u + q];
+                zr += buf[u].p.x * yk.x - buf[u].p.y * yk.y;
+                zi += buf[u].p.x * yk.y + buf[u].p.y * yk.x;
+            }
+            mma_step(buf[u], accR, accI, t3);
         }
-        mma_step(cur, accR, accI);
-        if (k0 + 8 < K) load_step(cur, pp, qp, k0 + 8);
-        if (WITHZ) {
-            const double2 yk = y[k0 + 4 + q];
-            zr += nxt.p.x * yk.x - nxt.p.y * yk.y;
-            zi += nxt.p.x * yk.y + nxt.p.y * yk.x;
-        }
-        mma_step(nxt, accR, accI);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const d4 a = accR[cb], b = accI[cb];
+        accR[cb] = a + b;
+        accI[cb] = t3[cb] - a + b;
     }
 }
 
