@@ -81,12 +81,48 @@ def cpu_baseline(inst, n_rows: int = 2000):
             "seconds_measured": round(t_pre * rows / inst.m + t_like, 2)}
 
 
+def precision_report(ctx, inst, T, nv, d, theta, logL64):
+    """A in FP32 and in split BF16 against the FP64 A of the same GPU path
+    (itself parity-checked against the oracle): relative Frobenius error of
+    A, |dlogL| over the batch, and the precompute time of each precision."""
+    import torch
+    stream = torch.cuda.current_stream()
+
+    def timed_pre(prec):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, prec=prec)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    rep = {"fp64_precompute_ms": timed_pre("fp64")}
+    A64 = ctx.export_precompute()[0]
+    nrm = torch.linalg.norm(A64).item()
+    for prec in ("fp32", "bf16x3"):
+        ms = timed_pre(prec)
+        A = ctx.export_precompute()[0]
+        rel = (torch.linalg.norm(A - A64).item()) / nrm
+        del A
+        L, info = ctx.loglike_batch(theta)
+        dl = (L - logL64).abs()
+        rep[prec] = {"rel_frob_A": rel, "max_abs_dlogL": dl.max().item(),
+                     "max_rel_dlogL": (dl / logL64.abs()).max().item(),
+                     "precompute_ms": ms, "info_nonzero": int((info != 0).sum().item())}
+    del A64
+    ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, prec="fp64")
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -175,6 +211,8 @@ def main():
         "loglike_evals_per_s": B / (like_ms / 1e3),
         "gated": None,
     }
+    if not args.no_precision:
+        out["precision"] = precision_report(ctx, inst, T, nv, d, theta, logL.clone())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst)
     else:

@@ -52,6 +52,9 @@ void free_problem(Context &c) {
     free_dev(c.bin_count);
     free_dev(c.invvar);
     free_dev(c.partial);
+    if (c.lowp) (void)hipFree(c.lowp);
+    c.lowp = nullptr;
+    c.lowp_bytes = 0;
     if (c.h_bin) (void)hipHostFree(c.h_bin);
     if (c.h_inv) (void)hipHostFree(c.h_inv);
     if (c.h_scale) (void)hipHostFree(c.h_scale);
@@ -253,12 +256,22 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     EOR_TRY(eor::launch_precompute_vectors(c, Td, ldT, noise_var, (const double2 *)d, c.invvar, c.partial,
                                            c.splits, s),
             "precompute vectors");
+    if (prec != EOR_PREC_FP64) {
+        const size_t need = eor::lowp_scratch_bytes(prec, m, c.n_pad);
+        if (c.lowp_bytes < need) {
+            if (c.lowp) (void)hipFree(c.lowp);
+            c.lowp = nullptr;
+            c.lowp_bytes = 0;
+            EOR_TRY(hipMalloc(&c.lowp, need), "hipMalloc reduced-precision W");
+            c.lowp_bytes = need;
+        }
+    }
     if (prec == EOR_PREC_FP64)
         EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, c.invvar, s), "precompute A (fp64)");
     else if (prec == EOR_PREC_FP32)
-        EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, c.invvar, s), "precompute A (fp32)");
+        EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (fp32)");
     else
-        EOR_TRY(eor::launch_precompute_bf16x3(c, Td, ldT, c.invvar, s), "precompute A (bf16x3)");
+        EOR_TRY(eor::launch_precompute_bf16x3(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (bf16x3)");
 #undef EOR_TRY
     c.ready = true;
     return EOR_OK;

@@ -54,6 +54,8 @@ struct Context {
     double *h_inv = nullptr;
     double *h_scale = nullptr;
     int32_t *h_count = nullptr;
+    void *lowp = nullptr;        // W in FP32 or in split BF16 planes (reduced-precision A)
+    size_t lowp_bytes = 0;
     int64_t alloc_m = 0, alloc_n = 0;
     int32_t alloc_k = -1;
     // per-theta workspace: one slot per resident workgroup
@@ -68,10 +70,11 @@ struct Context {
 // Kernel launchers (precompute.hip, likelihood.hip).
 hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ldT,
                                   const double *invvar, hipStream_t s);
+size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad);
 hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ldT,
-                                  const double *invvar, hipStream_t s);
+                                  const double *invvar, void *scratch, hipStream_t s);
 hipError_t launch_precompute_bf16x3(const Context &c, const double2 *T, int64_t ldT,
-                                    const double *invvar, hipStream_t s);
+                                    const double *invvar, void *scratch, hipStream_t s);
 hipError_t launch_precompute_vectors(const Context &c, const double2 *T, int64_t ldT,
                                      const double *noise_var, const double2 *d, double *invvar,
                                      double2 *partial, int splits, hipStream_t s);

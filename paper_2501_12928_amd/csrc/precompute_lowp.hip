@@ -1,0 +1,303 @@
+// Reduced-precision forms of A = W^H W, W = N^{-1/2} T (rows scaled by
+// 1/sigma_s), stored in FP64 in the same packed lower tiles as the FP64 path.
+//
+// FP32: W is formed in FP64 and rounded to complex64; each 64 x 64 tile is a
+//   sum of FP32 MFMA (16x16x4) products accumulated in FP32 over chunks of
+//   64 rows of W; the chunk partials are added into FP64 accumulators.
+// BF16x3: W is formed in FP64, rounded to FP32, and every real and imaginary
+//   part x is split into three bfloat16 terms x = h + m + l (+ a remainder
+//   below 2^-24 |x|); a real product x y keeps the six leading cross products
+//   hh' + hm' + mh' + hl' + mm' + lh' on BF16 MFMA (16x16x32) with FP32
+//   accumulation, and again the 64-row chunk partials go to FP64.
+//
+// Both MFMAs return D[4(l/16) + r][l%16] in register r (FP32 16x16x4 and
+// BF16 16x16x32), with the A operand lane l = A[l%16][k-group l/16] and the B
+// operand lane l = B[k-group l/16][l%16].
+#include "common.h"
+
+namespace eor {
+
+namespace {
+
+// Rows of W accumulated in FP32 before the partial goes to FP64. The FP32
+// error of a chunk grows with its length (positive diagonal terms make it
+// systematic); 64 rows keep logL about ten times closer to FP64 than 256 at
+// a negligible cost, and a multiple of 64 is what the split transpose needs.
+constexpr int CHUNK_ROWS = 64;
+
+__device__ inline f4 mfma32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+
+__device__ inline f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void tile_of(int64_t t, int64_t &i, int64_t &j) {
+    int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    i = r;
+    j = t - r * (r + 1) / 2;
+}
+
+// Store a tile held as FP64 accumulators: lane holds
+// A[64 ti + 16 w + l16][64 tj + 16 cb + 4 q + r].
+__device__ inline void store_tile(double2 *__restrict__ Ap, int64_t ti, int64_t tj, int64_t n,
+                                  const double (&sR)[4][4], const double (&sI)[4][4], int w, int l16,
+                                  int q) {
+    double2 *tile = Ap + tile_index(ti, tj) * TS2;
+    const int row = 16 * w + l16;
+    const int64_t grow = TS * ti + row;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = 16 * cb + 4 * q + r;
+            const int64_t gcol = TS * tj + col;
+            double2 v = make_double2(sR[cb][r], sI[cb][r]);
+            if (grow == gcol) v.y = 0.0;
+            if (grow >= n || gcol >= n) v = make_double2(grow == gcol ? 1.0 : 0.0, 0.0);
+            tile[col * TS + row] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- FP32 ----
+
+// W32[s][j] = complex64(T[s][j] / sigma_s), zero in the padding.
+__global__ void w32_kernel(const double2 *__restrict__ T, int64_t ldT, int64_t m, int64_t n,
+                           const double *__restrict__ invvar, int64_t m_pad, int64_t n_pad,
+                           float2 *__restrict__ W) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = blockIdx.y;
+    if (j >= n_pad) return;
+    for (int64_t ss = s; ss < m_pad; ss += gridDim.y) {
+        float2 v = make_float2(0.f, 0.f);
+        if (ss < m && j < n) {
+            const double2 t = T[ss * ldT + j];
+            const double sc = sqrt(invvar[ss]);
+            v = make_float2((float)(t.x * sc), (float)(t.y * sc));
+        }
+        W[ss * n_pad + j] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void herk_fp32_kernel(const float2 *__restrict__ W, int64_t m_pad,
+                                                        int64_t n_pad, int64_t n,
+                                                        double2 *__restrict__ Ap) {
+    int64_t ti, tj;
+    tile_of(blockIdx.x, ti, tj);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    // D[c][r] = sum_s b[s][c] conj(a[s][r]):  b = W[s][64 tj + c], a = W[s][64 ti + r]
+    const float2 *pa = W + (int64_t)q * n_pad + TS * ti + 16 * w + l16;
+    const float2 *pb = W + (int64_t)q * n_pad + TS * tj + l16;
+    double sR[4][4], sI[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sR[cb][r] = sI[cb][r] = 0.0;
+
+    for (int64_t c0 = 0; c0 < m_pad; c0 += CHUNK_ROWS) {
+        f4 aR[4], aI[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            aR[cb] = f4{0, 0, 0, 0};
+            aI[cb] = f4{0, 0, 0, 0};
+        }
+        for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 4) {
+            const float2 a = pa[s0 * n_pad];
+            float2 b[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) b[cb] = pb[s0 * n_pad + 16 * cb];
+            const float nai = -a.y;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                aR[cb] = mfma32(b[cb].x, a.x, aR[cb]);
+                aR[cb] = mfma32(b[cb].y, a.y, aR[cb]);
+                aI[cb] = mfma32(b[cb].y, a.x, aI[cb]);
+                aI[cb] = mfma32(b[cb].x, nai, aI[cb]);
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sR[cb][r] += (double)aR[cb][r];
+                sI[cb][r] += (double)aI[cb][r];
+            }
+    }
+    store_tile(Ap, ti, tj, n, sR, sI, w, l16, q);
+}
+
+// -------------------------------------------------------------- BF16x3 ----
+
+__device__ inline unsigned short bf16_bits(float x) {
+    // round to nearest even
+    unsigned int u = __float_as_uint(x);
+    const unsigned int lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+// Split planes, transposed: plane p (0..5 = re h, m, l, im h, m, l) holds
+// P[p][j][s] for s < m_pad (zero in the padding), so eight consecutive rows
+// s of one column are 16 contiguous bytes. One block transposes a 64 x 64
+// tile of W through LDS.
+__global__ __launch_bounds__(256) void split_kernel(const double2 *__restrict__ T, int64_t ldT,
+                                                    int64_t m, int64_t n,
+                                                    const double *__restrict__ invvar, int64_t m_pad,
+                                                    int64_t n_pad, unsigned short *__restrict__ P) {
+    __shared__ unsigned short sh[6][64][65];
+    const int64_t s0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int rr = ty; rr < 64; rr += 4) {
+        const int64_t s = s0 + rr, j = j0 + tx;
+        float xr = 0.f, xi = 0.f;
+        if (s < m && j < n) {
+            const double2 t = T[s * ldT + j];
+            const double sc = sqrt(invvar[s]);
+            xr = (float)(t.x * sc);
+            xi = (float)(t.y * sc);
+        }
+        const float xs[2] = {xr, xi};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float x = xs[c];
+            const unsigned short h = bf16_bits(x);
+            const float r1 = x - bf16_to_float(h);
+            const unsigned short mm = bf16_bits(r1);
+            const float r2 = r1 - bf16_to_float(mm);
+            const unsigned short l = bf16_bits(r2);
+            sh[3 * c + 0][tx][rr] = h;
+            sh[3 * c + 1][tx][rr] = mm;
+            sh[3 * c + 2][tx][rr] = l;
+        }
+    }
+    __syncthreads();
+    for (int cc = ty; cc < 64; cc += 4) {
+        const int64_t j = j0 + cc, s = s0 + tx;
+        if (j < n_pad && s < m_pad) {
+#pragma unroll
+            for (int p = 0; p < 6; ++p) P[((int64_t)p * n_pad + j) * m_pad + s] = sh[p][cc][tx];
+        }
+    }
+}
+
+__device__ inline bf8 ld_bf8(const unsigned short *p) {
+    const s8v v = *reinterpret_cast<const s8v *>(p);
+    return __builtin_bit_cast(bf8, v);
+}
+
+__device__ inline bf8 neg_bf8(bf8 x) {
+    s8v v = __builtin_bit_cast(s8v, x);
+    v ^= (short)0x8000;
+    return __builtin_bit_cast(bf8, v);
+}
+
+// x y with x = xh + xm + xl, y = yh + ym + yl: the six leading products.
+__device__ inline f4 prod6(const bf8 (&x)[3], const bf8 (&y)[3], f4 acc) {
+    acc = mfma_bf16(x[2], y[0], acc);
+    acc = mfma_bf16(x[1], y[1], acc);
+    acc = mfma_bf16(x[0], y[2], acc);
+    acc = mfma_bf16(x[1], y[0], acc);
+    acc = mfma_bf16(x[0], y[1], acc);
+    acc = mfma_bf16(x[0], y[0], acc);
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *__restrict__ P,
+                                                          int64_t m_pad, int64_t n_pad, int64_t n,
+                                                          double2 *__restrict__ Ap) {
+    int64_t ti, tj;
+    tile_of(blockIdx.x, ti, tj);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    const int64_t plane = n_pad * m_pad;
+    // B operand (a = W[s][64 ti + 16 w + l16]), A operands (b = W[s][64 tj + 16 cb + l16])
+    const unsigned short *pa = P + (TS * ti + 16 * w + l16) * m_pad + 8 * q;
+    const unsigned short *pb = P + (TS * tj + l16) * m_pad + 8 * q;
+    double sR[4][4], sI[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sR[cb][r] = sI[cb][r] = 0.0;
+
+    for (int64_t c0 = 0; c0 < m_pad; c0 += CHUNK_ROWS) {
+        f4 aR[4], aI[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            aR[cb] = f4{0, 0, 0, 0};
+            aI[cb] = f4{0, 0, 0, 0};
+        }
+        for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 32) {
+            bf8 ar[3], ai[3], nai[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                ar[t] = ld_bf8(pa + t * plane + s0);
+                ai[t] = ld_bf8(pa + (3 + t) * plane + s0);
+                nai[t] = neg_bf8(ai[t]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                bf8 br[3], bi[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    br[t] = ld_bf8(pb + 16 * cb * m_pad + t * plane + s0);
+                    bi[t] = ld_bf8(pb + 16 * cb * m_pad + (3 + t) * plane + s0);
+                }
+                // re: br ar + bi ai;  im: bi ar - br ai
+                aR[cb] = prod6(br, ar, aR[cb]);
+                aR[cb] = prod6(bi, ai, aR[cb]);
+                aI[cb] = prod6(bi, ar, aI[cb]);
+                aI[cb] = prod6(br, nai, aI[cb]);
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sR[cb][r] += (double)aR[cb][r];
+                sI[cb][r] += (double)aI[cb][r];
+            }
+    }
+    store_tile(Ap, ti, tj, n, sR, sI, w, l16, q);
+}
+
+}  // namespace
+
+size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad) {
+    const int64_t m_pad = (m + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
+    if (prec == EOR_PREC_FP32) return (size_t)m_pad * n_pad * sizeof(float2);
+    if (prec == EOR_PREC_BF16X3) return (size_t)6 * m_pad * n_pad * sizeof(unsigned short);
+    return 0;
+}
+
+hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ldT, const double *invvar,
+                                  void *scratch, hipStream_t s) {
+    const int64_t m_pad = (c.m + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
+    float2 *W = (float2 *)scratch;
+    const unsigned gy = (unsigned)(m_pad < 65535 ? m_pad : 65535);
+    hipLaunchKernelGGL(w32_kernel, dim3((unsigned)((c.n_pad + 255) / 256), gy), dim3(256), 0, s, T, ldT,
+                       c.m, c.n, invvar, m_pad, c.n_pad, W);
+    hipLaunchKernelGGL(herk_fp32_kernel, dim3((unsigned)n_tiles(c.N)), dim3(256), 0, s, W, m_pad, c.n_pad,
+                       c.n, c.A);
+    return hipGetLastError();
+}
+
+hipError_t launch_precompute_bf16x3(const Context &c, const double2 *T, int64_t ldT, const double *invvar,
+                                    void *scratch, hipStream_t s) {
+    const int64_t m_pad = (c.m + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
+    unsigned short *P = (unsigned short *)scratch;
+    hipLaunchKernelGGL(split_kernel, dim3((unsigned)(c.n_pad / 64), (unsigned)(m_pad / 64)), dim3(256), 0, s,
+                       T, ldT, c.m, c.n, invvar, m_pad, c.n_pad, P);
+    hipLaunchKernelGGL(herk_bf16x3_kernel, dim3((unsigned)n_tiles(c.N)), dim3(256), 0, s, P, m_pad, c.n_pad,
+                       c.n, c.A);
+    return hipGetLastError();
+}
+
+}  // namespace eor
