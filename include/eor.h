@@ -139,6 +139,60 @@ eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *d
 /* Problem sizes of a context after eor_precompute: m, n, n_k (any may be NULL). */
 eor_status eor_shape(const eor_ctx *ctx, int64_t *m, int64_t *n, int32_t *n_k);
 
+/*
+ * Groups: many datasets of uneven size (e.g. independent frequency
+ * sub-bands, each with its own T, noise, data and bins) evaluated together.
+ * One eor_group_loglike call is one persistent launch: a fixed set of
+ * resident workgroups takes (instance, theta) tasks, longest first, until all
+ * are done, so small and large problems share the GPU without a tail per
+ * dataset.
+ *
+ * eor_group_create: n_inst (1..64) contexts on one device, each precomputed
+ * before every eor_group_loglike call. The group keeps pointers to the
+ * contexts (they must outlive it) and owns its own workspace.
+ * Errors: EOR_ERR_ARG, EOR_ERR_OOM, EOR_ERR_HIP.
+ */
+eor_status eor_group_create(int32_t n_inst, eor_ctx *const *insts, eor_group **out);
+
+/* Free a group (not its contexts). NULL is a no-op. */
+void eor_group_destroy(eor_group *g);
+
+/*
+ * logL for every instance: B, theta, logL and info are host arrays of length
+ * n_inst; theta[i] is a device double [B[i] x n_k(i)], logL[i] a device
+ * double [B[i]], info NULL or info[i] a device int32 [B[i]] (or NULL), with
+ * the meaning of eor_loglike_batch. The launch is captured once into a HIP
+ * graph and replayed while the sizes and pointers stay the same (see
+ * eor_group_set_graph). Synchronises the stream before it starts (the
+ * per-call descriptors are staged in pinned memory).
+ * Errors: EOR_ERR_ARG, EOR_ERR_STATE (an instance without precompute),
+ * EOR_ERR_OOM, EOR_ERR_HIP.
+ */
+eor_status eor_group_loglike(eor_group *g, const int64_t *B, const double *const *theta,
+                             double *const *logL, int32_t *const *info, void *stream);
+
+/* Enable (default) or disable graph capture and replay for this group. */
+eor_status eor_group_set_graph(eor_group *g, int32_t enable);
+
+/* Current launch choices of the group, and how many times it launched a
+ * graph and captured one so far (any output may be NULL). */
+eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per_cu,
+                            int64_t *graph_launches, int64_t *graph_captures);
+
+/*
+ * Autotuner: times the group on the given batch (same arguments as
+ * eor_group_loglike, outputs discarded) for every candidate launch (panel
+ * prefetch depth 2 or 4 k-steps x 1 or 2 theta in flight per CU) and keeps
+ * the fastest. With cache_path (may be NULL), the choice is stored in a JSON
+ * file keyed by "<gfx arch>|<size bucket of the largest n: n<=512, n<=1024,
+ * n<=2048, n<=4096, n>4096>|<single or group>", and an existing entry is
+ * used without timing unless force != 0. A lone dataset is tuned as a
+ * one-instance group. Synchronises the stream.
+ * Errors: as eor_group_loglike; EOR_ERR_ARG if the cache cannot be written.
+ */
+eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *theta,
+                        const char *cache_path, int32_t force, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

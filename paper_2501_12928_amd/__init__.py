@@ -56,8 +56,18 @@ def lib() -> ctypes.CDLL:
         L.eor_loglike_terms.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
         L.eor_export_precompute.argtypes = [_P, _P, _I64, _P, _P, _P]
         L.eor_shape.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]
+        L.eor_group_create.argtypes = [_I32, ctypes.POINTER(_P), ctypes.POINTER(_P)]
+        L.eor_group_destroy.argtypes = [_P]
+        L.eor_group_destroy.restype = None
+        L.eor_group_loglike.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                        ctypes.POINTER(_P), _P]
+        L.eor_group_set_graph.argtypes = [_P, _I32]
+        L.eor_group_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                                       ctypes.POINTER(_I64)]
+        L.eor_autotune.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.c_char_p, _I32, _P]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
-                     "eor_export_precompute", "eor_shape"):
+                     "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
+                     "eor_group_set_graph", "eor_group_tuning", "eor_autotune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -163,6 +173,70 @@ class Context:
         check(lib().eor_export_precompute(self._h, A.data_ptr(), self.n, dbar.data_ptr(), sc,
                                           _stream(stream)))
         return A, dbar, sc[0], sc[1]
+
+
+class Group:
+    """Several precomputed contexts evaluated in one persistent launch."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        n = len(self.contexts)
+        arr = (_P * n)(*[c.handle for c in self.contexts])
+        self._h = _P()
+        check(lib().eor_group_create(n, arr, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().eor_group_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _arrays(self, thetas):
+        import torch
+        n = len(self.contexts)
+        if len(thetas) != n:
+            raise ValueError("one theta batch per context")
+        th = [_dev(t, torch.float64) for t in thetas]
+        B = (_I64 * n)(*[t.shape[0] for t in th])
+        tp = (_P * n)(*[t.data_ptr() for t in th])
+        return th, B, tp
+
+    def loglike(self, thetas, stream=None, with_info=True, outs=None, infos=None):
+        """Lists of logL (and info) device tensors, one per context. Passing
+        the previous call's `outs`/`infos` keeps the pointers unchanged, so
+        the captured graph is replayed as is."""
+        import torch
+        th, B, tp = self._arrays(thetas)
+        if outs is None:
+            outs = [torch.empty(t.shape[0], dtype=torch.float64, device=t.device) for t in th]
+        if infos is None:
+            infos = [torch.empty(t.shape[0], dtype=torch.int32, device=t.device) for t in th]
+        n = len(th)
+        op = (_P * n)(*[o.data_ptr() for o in outs])
+        ip = (_P * n)(*[i.data_ptr() for i in infos]) if with_info else None
+        check(lib().eor_group_loglike(self._h, B, tp, op, ip, _stream(stream)))
+        return (outs, infos) if with_info else outs
+
+    def set_graph(self, enable: bool):
+        check(lib().eor_group_set_graph(self._h, 1 if enable else 0))
+
+    def tuning(self):
+        """(prefetch stages, workgroups per CU, graph launches, graph captures)."""
+        s, w, r, c = _I32(), _I32(), _I64(), _I64()
+        check(lib().eor_group_tuning(self._h, ctypes.byref(s), ctypes.byref(w), ctypes.byref(r),
+                                     ctypes.byref(c)))
+        return s.value, w.value, r.value, c.value
+
+    def autotune(self, thetas, cache_path=None, force=False, stream=None):
+        th, B, tp = self._arrays(thetas)
+        cp = None if cache_path is None else str(cache_path).encode()
+        check(lib().eor_autotune(self._h, B, tp, cp, 1 if force else 0, _stream(stream)))
+        return self.tuning()[:2]
 
 
 def version() -> str:

@@ -1,4 +1,5 @@
 // C ABI of libeor: argument checking, device memory, and launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,13 +15,39 @@ static thread_local std::string g_error;
 
 void set_error(const std::string &msg) { g_error = msg; }
 
+eor_status fail_status(eor_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+eor_status hip_status(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? EOR_ERR_OOM : EOR_ERR_HIP;
+}
+
+int64_t resident_per_cu(const Tuning &t) {
+    return std::min<int64_t>(t.wg_per_cu, like_max_resident_per_cu());
+}
+
+InstDesc inst_desc(const Context &c) {
+    InstDesc d;
+    d.A = c.A;
+    d.dbar = c.dbar;
+    d.coef_bin = c.coef_bin;
+    d.coef_inv = c.coef_inv;
+    d.bin_scale = c.bin_scale;
+    d.bin_count = c.bin_count;
+    d.scal = c.scal;
+    d.khost = c.khost;
+    d.fixed_logv = c.fixed_logv;
+    d.n_k = c.n_k;
+    d.N = (int32_t)c.N;
+    return d;
+}
+
 }  // namespace eor
 
 using eor::Context;
-
-struct eor_ctx {
-    Context c;
-};
 
 namespace {
 
@@ -52,6 +79,10 @@ void free_problem(Context &c) {
     free_dev(c.bin_count);
     free_dev(c.invvar);
     free_dev(c.partial);
+    free_dev(c.d_inst);
+    free_dev(c.counter);
+    if (c.h_inst) (void)hipHostFree(c.h_inst);
+    c.h_inst = nullptr;
     if (c.lowp) (void)hipFree(c.lowp);
     c.lowp = nullptr;
     c.lowp_bytes = 0;
@@ -235,6 +266,9 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
         EOR_TRY(hipHostMalloc((void **)&c.h_inv, c.n_pad * sizeof(double)), "hipHostMalloc");
         EOR_TRY(hipHostMalloc((void **)&c.h_scale, nk1 * sizeof(double)), "hipHostMalloc");
         EOR_TRY(hipHostMalloc((void **)&c.h_count, nk1 * sizeof(int32_t)), "hipHostMalloc");
+        EOR_TRY(hipHostMalloc((void **)&c.h_inst, sizeof(eor::InstDesc)), "hipHostMalloc");
+        EOR_TRY(hipMalloc(&c.d_inst, sizeof(eor::InstDesc)), "hipMalloc descriptor");
+        EOR_TRY(hipMalloc(&c.counter, sizeof(unsigned int)), "hipMalloc counter");
         c.alloc_m = m;
         c.alloc_n = n;
         c.alloc_k = n_k;
@@ -251,6 +285,8 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     EOR_TRY(hipMemcpyAsync(c.coef_inv, c.h_inv, c.n_pad * sizeof(double), hipMemcpyHostToDevice, s), "copy fixed");
     EOR_TRY(hipMemcpyAsync(c.bin_scale, c.h_scale, nk1 * sizeof(double), hipMemcpyHostToDevice, s), "copy scales");
     EOR_TRY(hipMemcpyAsync(c.bin_count, c.h_count, nk1 * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy counts");
+    *c.h_inst = eor::inst_desc(c);
+    EOR_TRY(hipMemcpyAsync(c.d_inst, c.h_inst, sizeof(eor::InstDesc), hipMemcpyHostToDevice, s), "copy descriptor");
 
     const double2 *Td = (const double2 *)T;
     EOR_TRY(eor::launch_precompute_vectors(c, Td, ldT, noise_var, (const double2 *)d, c.invvar, c.partial,
@@ -282,16 +318,27 @@ static eor_status loglike_impl(eor_ctx *ctx, int64_t B, const double *theta, dou
     if (!ctx) return fail(EOR_ERR_ARG, "eor_loglike_batch: ctx is NULL");
     Context &c = ctx->c;
     if (!c.ready) return fail(EOR_ERR_STATE, "eor_loglike_batch: call eor_precompute first");
-    if (B < 0) return fail(EOR_ERR_ARG, "eor_loglike_batch: B < 0");
+    if (B < 0 || B > (int64_t)1 << 30) return fail(EOR_ERR_ARG, "eor_loglike_batch: need 0 <= B <= 2^30");
     if (B == 0) return EOR_OK;
     if ((!theta && c.n_k > 0) || !logL) return fail(EOR_ERR_ARG, "eor_loglike_batch: NULL array");
     DeviceGuard g(c.device);
-    const int64_t resident = (int64_t)eor::like_max_resident_per_cu() * c.num_cu;
+    const int64_t resident = eor::resident_per_cu(c.tune) * c.num_cu;
     const int64_t want = B < resident ? B : resident;
     eor_status st = ensure_work(c, want);
     if (st != EOR_OK) return st;
+    eor::LikeParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.inst = c.d_inst;
+    p.task = nullptr;
+    p.ntask = B;
+    p.counter = c.counter;
+    p.Lw = c.Lw;
+    p.slot_tiles = c.slot_tiles;
+    p.yw = c.yw;
+    p.slot_y = c.slot_y;
+    p.call[0] = eor::CallDesc{theta, logL, info, terms};
     const int64_t grid = want < c.slots ? want : c.slots;
-    hipError_t e = eor::launch_likelihood(c, B, theta, logL, info, terms, grid, (hipStream_t)stream);
+    hipError_t e = eor::launch_likelihood(p, c.tune.stages, grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "likelihood launch");
     return EOR_OK;
 }

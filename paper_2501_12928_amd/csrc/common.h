@@ -28,6 +28,52 @@ __host__ __device__ inline int64_t n_tiles(int64_t N) { return N * (N + 1) / 2; 
 
 void set_error(const std::string &msg);
 
+// Everything the likelihood kernel needs about one dataset (one context).
+struct InstDesc {
+    const double2 *A;          // packed lower tiles
+    const double2 *dbar;       // [n_pad]
+    const int32_t *coef_bin;   // [n_pad]: bin, -1 fixed, -2 padding
+    const double *coef_inv;    // [n_pad]: 1/v_j of fixed coefficients
+    const double *bin_scale;   // [n_k]
+    const int32_t *bin_count;  // [n_k]
+    const double *scal;        // [2]: c, -sum ln sigma^2
+    double khost;              // -m ln(pi)
+    double fixed_logv;         // sum over fixed coefficients of ln v_j
+    int32_t n_k;
+    int32_t N;                 // tiles per side
+};
+
+// Per-call arrays of one instance: theta [B x n_k], logL [B], info [B] or
+// NULL, terms [B x 4] or NULL.
+struct CallDesc {
+    const double *theta;
+    double *logL;
+    int32_t *info;
+    double *terms;
+};
+
+// Largest number of instances one launch serves (the per-call table travels
+// in the kernel arguments).
+constexpr int MAX_INST = 64;
+
+struct LikeParams {
+    const InstDesc *inst;         // device [n_inst]
+    const int2 *task;             // device [ntask] (instance, theta index), or NULL: (0, t)
+    int64_t ntask;                // < 2^31
+    unsigned int *counter;        // next task; zeroed by the launch
+    double2 *Lw;                  // per-slot packed tiles of L
+    int64_t slot_tiles;
+    double2 *yw;                  // per-slot y
+    int64_t slot_y;
+    CallDesc call[MAX_INST];
+};
+
+// Launch choices the autotuner picks between.
+struct Tuning {
+    int stages = 4;      // register prefetch depth of the panel update (2 or 4)
+    int wg_per_cu = 2;   // resident workgroups (theta in flight) per CU (1 or 2)
+};
+
 // State behind an eor_ctx handle.
 struct Context {
     int device = 0;
@@ -45,6 +91,9 @@ struct Context {
     double *coef_inv = nullptr;  // [n_pad]: 1/v_j for fixed coefficients, else 0
     double *bin_scale = nullptr; // [n_k]
     int32_t *bin_count = nullptr;// [n_k]
+    InstDesc *d_inst = nullptr;  // device copy of this dataset's descriptor
+    unsigned int *counter = nullptr;
+    Tuning tune;
     // precompute temporaries, kept so a repeated precompute needs no allocation
     double *invvar = nullptr;    // [m]
     double2 *partial = nullptr;  // [splits * n]
@@ -54,6 +103,7 @@ struct Context {
     double *h_inv = nullptr;
     double *h_scale = nullptr;
     int32_t *h_count = nullptr;
+    InstDesc *h_inst = nullptr;
     void *lowp = nullptr;        // W in FP32 or in split BF16 planes (reduced-precision A)
     size_t lowp_bytes = 0;
     int64_t alloc_m = 0, alloc_n = 0;
@@ -66,6 +116,11 @@ struct Context {
     int64_t slot_y = 0;          // complex entries of y per slot
     size_t work_limit = 0;       // bytes; 0 = no limit
 };
+
+// Shared helpers of the ABI layer (abi.hip).
+eor_status fail_status(eor_status st, const std::string &msg);
+eor_status hip_status(hipError_t e, const char *what);
+int64_t resident_per_cu(const Tuning &t);
 
 // Kernel launchers (precompute.hip, likelihood.hip).
 hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ldT,
@@ -80,9 +135,13 @@ hipError_t launch_precompute_vectors(const Context &c, const double2 *T, int64_t
                                      double2 *partial, int splits, hipStream_t s);
 hipError_t launch_export_A(const Context &c, double2 *out, int64_t ldA, hipStream_t s);
 
-struct LikeArgs;
 int like_max_resident_per_cu();
-hipError_t launch_likelihood(const Context &c, int64_t B, const double *theta, double *logL,
-                             int32_t *info, double *terms, int64_t grid, hipStream_t s);
+hipError_t launch_likelihood(const LikeParams &p, int stages, int64_t grid, hipStream_t s);
+InstDesc inst_desc(const Context &c);
 
 }  // namespace eor
+
+// The handle behind eor_ctx.
+struct eor_ctx {
+    eor::Context c;
+};

@@ -42,6 +42,13 @@ __device__ inline d4 mfma64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Every value that steers a loop or branch containing a barrier is passed
+// through readfirstlane, so the compiler sees it as wave-uniform and emits
+// scalar branches. Left as per-lane values (they come from LDS or global
+// memory), the structurizer may place a barrier inside a per-lane loop and
+// different waves then execute different numbers of barriers.
+__device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // Hides a lane-dependent value from loop-invariant code motion, so that the
 // compiler forms tile addresses as one lane offset plus constants where they
 // are used instead of hoisting one register per address out of the loops.
@@ -50,38 +57,15 @@ __device__ inline int opaque(int x) {
     return x;
 }
 
-struct LikeParams {
-    const double2 *A;
-    const double2 *dbar;
-    const int32_t *coef_bin;
-    const double *coef_inv;
-    const double *bin_scale;
-    const int32_t *bin_count;
-    const double *scal;
-    double khost;            // -m ln(pi)
-    double khost_fixed_logv; // sum over fixed coefficients of ln v_j
-    const double *theta;
-    int32_t n_k;
-    int64_t B;
-    int64_t N;
-    double2 *Lw;
-    int64_t slot_tiles;
-    double2 *yw;
-    int64_t slot_y;
-    double *logL;
-    int32_t *info;
-    double *terms;
-};
-
 // Operands of one k-step (4 consecutive columns k0..k0+3 of the panels).
 struct Step {
     double2 p;     // P[16w + l16][k0 + q]
     double2 qv[4]; // Q[16cb + l16][k0 + q]
 };
 
-// Register prefetch depth of the panel update, in k-steps. The panels come
-// from HBM; four steps in flight cover its latency at two waves per SIMD.
-constexpr int STAGES = 4;
+// The register prefetch depth of the panel update (k-steps in flight) is a
+// template parameter; four steps cover HBM latency at two waves per SIMD on
+// the large problems, and the autotuner may choose two.
 
 __device__ inline void load_step(Step &s, const double2 *__restrict__ pp, const double2 *__restrict__ qp,
                                  int64_t k0) {
@@ -108,7 +92,7 @@ __device__ inline void mma_step(const Step &s, d4 t1[4], d4 t2[4], d4 t3[4]) {
 // With WITHZ, also the partial z[i] = sum_k P[i][k] y[k] of the forward
 // substitution. The four waves re-align once per 64 columns so that the
 // column panel Q, which all of them read, is fetched from HBM once.
-template <bool WITHZ>
+template <bool WITHZ, int STAGES>
 __device__ inline void panel_update(const double2 *__restrict__ P, const double2 *__restrict__ Q,
                                     const double2 *__restrict__ y, int64_t K, int w, int l16, int q,
                                     d4 accR[4], d4 accI[4], double &zr, double &zi) {
@@ -147,55 +131,75 @@ __device__ inline void panel_update(const double2 *__restrict__ P, const double2
     }
 }
 
+template <int STAGES>
 __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
     __shared__ double2 Dt[TS2];   // diagonal tile: D, then L_jj, then L_jj^{-1}
     __shared__ double2 wv[TS];    // dbar_j - z, then y_j
     __shared__ double dg[TS];     // pivots of the current diagonal tile
     __shared__ double red[TS];    // |y_j|^2 per row
+    __shared__ int task_sh;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-    const int64_t N = a.N;
     double2 *L = a.Lw + (int64_t)blockIdx.x * a.slot_tiles * TS2;
     double2 *yv = a.yw + (int64_t)blockIdx.x * a.slot_y;
 
-    for (int64_t t = blockIdx.x; t < a.B; t += gridDim.x) {
-        const double *th = a.theta + t * a.n_k;
+    // Persistent workgroup: take tasks in list order (the host sorts them
+    // longest first) until the list is exhausted.
+    for (;;) {
+        if (tid == 0) task_sh = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int t = uniform(task_sh);
+        __syncthreads();
+        if (t >= a.ntask) break;
+        int inst = 0;
+        int64_t bt = t;
+        if (a.task) {
+            const int2 td = a.task[t];
+            inst = uniform(td.x);
+            bt = uniform(td.y);
+        }
+        const InstDesc I = a.inst[inst];
+        const CallDesc C = a.call[inst];
+        const int64_t N = I.N;
+        const double *th = C.theta + bt * I.n_k;
         // ln det Phi over the binned coefficients, and the theta check.
         bool ok = true;
         double ldp = 0.0;
-        for (int b = 0; b < a.n_k; ++b) {
+        for (int b = 0; b < I.n_k; ++b) {
             const double tb = th[b];
             if (!isfinite(tb)) ok = false;
-            if (a.bin_count[b] > 0) {
-                const double phi = a.bin_scale[b] * exp10(tb);
+            if (I.bin_count[b] > 0) {
+                const double phi = I.bin_scale[b] * exp10(tb);
                 if (!(phi > 0.0) || !isfinite(phi)) ok = false;
-                ldp += (double)a.bin_count[b] * log(phi);
+                ldp += (double)I.bin_count[b] * log(phi);
             }
         }
-        if (!ok) {
-            if (tid == 0) {
-                a.logL[t] = -INFINITY;
-                if (a.info) a.info[t] = -1;
-                if (a.terms) {
-                    for (int e = 0; e < 4; ++e) a.terms[4 * t + e] = NAN;
-                }
+        // An invalid theta still falls through to the barrier that closes
+        // the task: every lane must reconverge there before tid 0 fetches the
+        // next task, or the lanes that skip tid 0's stores can be scheduled
+        // around the loop on their own and spin on the old task index.
+        const bool valid = uniform(ok ? 1 : 0) != 0;
+        if (!valid && tid == 0) {
+            C.logL[bt] = -INFINITY;
+            if (C.info) C.info[bt] = -1;
+            if (C.terms) {
+                for (int e = 0; e < 4; ++e) C.terms[4 * bt + e] = NAN;
             }
-            continue;
         }
 
         double logdet = 0.0, quad = 0.0;  // meaningful in thread 0 only
         int failed = 0;
 
-        for (int64_t j = 0; j < N && !failed; ++j) {
+        for (int64_t j = 0; valid && j < N && !failed; ++j) {
             __syncthreads();  // previous column's readers of Dt are done
             const double2 *panel_j = L + tile_index(j, 0) * TS2;
 
             // ---- diagonal tile --------------------------------------------
             d4 accR[4], accI[4];
             double zr = 0.0, zi = 0.0;
-            panel_update<true>(panel_j, panel_j, yv, j * TS, w, l16, q, accR, accI, zr, zi);
+            panel_update<true, STAGES>(panel_j, panel_j, yv, j * TS, w, l16, q, accR, accI, zr, zi);
             {
-                const double2 *Ajj = a.A + tile_index(j, j) * TS2;
+                const double2 *Ajj = I.A + tile_index(j, j) * TS2;
                 const int lo = opaque(q * TS + 16 * w + l16);  // [16w + l16][q], column-major
                 const int dq = opaque(l16 - q);                // row == col iff cb == w, 4r == dq
                 const int row = 16 * w + l16;
@@ -209,8 +213,8 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
                         v.y -= accI[cb][r];
                         if (cb == w && dq == 4 * r) {
                             const int64_t g = j * TS + row;
-                            const int32_t b = a.coef_bin[g];
-                            const double ip = b >= 0 ? 1.0 / (a.bin_scale[b] * exp10(th[b])) : a.coef_inv[g];
+                            const int32_t b = I.coef_bin[g];
+                            const double ip = b >= 0 ? 1.0 / (I.bin_scale[b] * exp10(th[b])) : I.coef_inv[g];
                             v.x += ip;
                         }
                         Dt[off] = v;
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
                 zr += __shfl_xor(zr, 32);
                 zi += __shfl_xor(zi, 32);
                 if (q == 0) {
-                    const double2 db = a.dbar[j * TS + row];
+                    const double2 db = I.dbar[j * TS + row];
                     wv[row] = make_double2(db.x - zr, db.y - zi);
                 }
             }
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
                 for (int c = 0; c < TS; ++c) {
                     __syncthreads();
                     const double dcc = Dt[c * TS + c].x;
-                    if (!(dcc > 0.0) || !isfinite(dcc)) {
+                    if (uniform((!(dcc > 0.0) || !isfinite(dcc)) ? 1 : 0)) {
                         failed = (int)(j * TS + c + 1);
                         break;
                     }
@@ -321,8 +325,8 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
             // ---- tiles below the diagonal ---------------------------------
             for (int64_t i = j + 1; i < N; ++i) {
                 const double2 *panel_i = L + tile_index(i, 0) * TS2;
-                panel_update<false>(panel_i, panel_j, nullptr, j * TS, w, l16, q, accR, accI, zr, zi);
-                const double2 *Aij = a.A + tile_index(i, j) * TS2;
+                panel_update<false, STAGES>(panel_i, panel_j, nullptr, j * TS, w, l16, q, accR, accI, zr, zi);
+                const double2 *Aij = I.A + tile_index(i, j) * TS2;
                 const int lo = opaque(q * TS + 16 * w + l16);
                 // X = A_ij - S, in the accumulator layout
 #pragma unroll
@@ -362,62 +366,47 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
             }
         }
 
-        if (tid == 0) {
-            const double c = a.scal[0];
+        if (valid && tid == 0) {
+            const double c = I.scal[0];
             if (failed) {
-                a.logL[t] = -INFINITY;
-                if (a.info) a.info[t] = failed;
-                if (a.terms) {
-                    for (int e = 0; e < 4; ++e) a.terms[4 * t + e] = NAN;
+                C.logL[bt] = -INFINITY;
+                if (C.info) C.info[bt] = failed;
+                if (C.terms) {
+                    for (int e = 0; e < 4; ++e) C.terms[4 * bt + e] = NAN;
                 }
             } else {
-                const double ldphi = ldp + a.khost_fixed_logv;
-                a.logL[t] = (a.khost + a.scal[1]) - ldphi - logdet - (c - quad);
-                if (a.info) a.info[t] = 0;
-                if (a.terms) {
-                    a.terms[4 * t + 0] = logdet;
-                    a.terms[4 * t + 1] = quad;
-                    a.terms[4 * t + 2] = ldphi;
-                    a.terms[4 * t + 3] = c;
+                const double ldphi = ldp + I.fixed_logv;
+                C.logL[bt] = (I.khost + I.scal[1]) - ldphi - logdet - (c - quad);
+                if (C.info) C.info[bt] = 0;
+                if (C.terms) {
+                    C.terms[4 * bt + 0] = logdet;
+                    C.terms[4 * bt + 1] = quad;
+                    C.terms[4 * bt + 2] = ldphi;
+                    C.terms[4 * bt + 3] = c;
                 }
             }
         }
-        __syncthreads();  // slot workspace is reused by the next theta
+        __syncthreads();  // slot workspace is reused by the next task
     }
 }
+
+__global__ void zero_counter_kernel(unsigned int *counter) { *counter = 0u; }
 
 }  // namespace
 
 int like_max_resident_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, likelihood_kernel, NT, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, likelihood_kernel<4>, NT, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_likelihood(const Context &c, int64_t B, const double *theta, double *logL,
-                             int32_t *info, double *terms, int64_t grid, hipStream_t s) {
-    LikeParams p;
-    p.A = c.A;
-    p.dbar = c.dbar;
-    p.coef_bin = c.coef_bin;
-    p.coef_inv = c.coef_inv;
-    p.bin_scale = c.bin_scale;
-    p.bin_count = c.bin_count;
-    p.scal = c.scal;
-    p.khost = c.khost;
-    p.khost_fixed_logv = c.fixed_logv;
-    p.theta = theta;
-    p.n_k = c.n_k;
-    p.B = B;
-    p.N = c.N;
-    p.Lw = c.Lw;
-    p.slot_tiles = c.slot_tiles;
-    p.yw = c.yw;
-    p.slot_y = c.slot_y;
-    p.logL = logL;
-    p.info = info;
-    p.terms = terms;
-    hipLaunchKernelGGL(likelihood_kernel, dim3((unsigned)grid), dim3(NT), 0, s, p);
+hipError_t launch_likelihood(const LikeParams &p, int stages, int64_t grid, hipStream_t s) {
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, p.counter);
+    if (stages == 2)
+        hipLaunchKernelGGL(likelihood_kernel<2>, dim3((unsigned)grid), dim3(NT), 0, s, p);
+    else
+        hipLaunchKernelGGL(likelihood_kernel<4>, dim3((unsigned)grid), dim3(NT), 0, s, p);
     return hipGetLastError();
 }
 

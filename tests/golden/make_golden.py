@@ -6,6 +6,7 @@ only. Run from the repository root:
     python tests/golden/make_golden.py digests
     python tests/golden/make_golden.py c1 [n_sample]
     python tests/golden/make_golden.py c3 [n_sample]
+    python tests/golden/make_golden.py c2
 """
 import json
 import os
@@ -59,9 +60,31 @@ def sampled(config_id, n_sample):
         json.dump(out, f, indent=1)
 
 
+def group_sampled(pick=(11, 17, 9), n_theta=2):
+    """Oracle logL for the first theta of three of the 48 uneven sub-band
+    instances (the smallest, the median and the largest n)."""
+    import oracle
+    orc = oracle.get()
+    out = {"instances": {}}
+    for idx, inst in enumerate(synth.gen_group()):
+        if idx not in pick:
+            continue
+        t0 = time.time()
+        logL, info = orc.loglike_instance(inst, theta=inst.theta[:n_theta])
+        out["instances"][str(idx)] = {"n": inst.n, "m": inst.m, "n_k": inst.n_k,
+                                      "B": int(inst.theta.shape[0]), "digest": inst.digest(),
+                                      "logL": logL.tolist(), "info": info.tolist(),
+                                      "oracle_seconds": time.time() - t0}
+        print(idx, inst.n, time.time() - t0, flush=True)
+    with open(os.path.join(HERE, "c2_oracle_sample.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1]
     if what == "digests":
         digests()
+    elif what == "c2":
+        group_sampled()
     else:
         sampled(int(what[1:]), int(sys.argv[2]) if len(sys.argv) > 2 else 8)
