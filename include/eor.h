@@ -193,6 +193,111 @@ eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per
 eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *theta,
                         const char *cache_path, int32_t force, void *stream);
 
+/*
+ * Surrogate of logL(theta): an ensemble of n_members fully connected
+ * networks n_in -> hidden -> hidden -> 1 with GELU (exact erf form) after
+ * each hidden layer, FP32, trained by the library's own forward, backward
+ * and Adam kernels on exact evaluations, and used to gate sampler proposals:
+ * an ensemble spread above a threshold falls back to the exact likelihood,
+ * and every accepted point is judged by the exact likelihood.
+ *
+ * Parameters of one member, flat FP32, row-major matrices:
+ *   W1 [hidden x n_in], b1 [hidden], W2 [hidden x hidden], b2 [hidden],
+ *   W3 [hidden], b3 [1]; members follow one another.
+ * Inputs: theta mapped from the prior box [lo, hi] to [-1, 1]. Targets:
+ * logL standardised by the training mean and standard deviation. Ensemble
+ * mean and spread are reported in logL units; the spread is the population
+ * standard deviation (ddof = 0) over the members.
+ */
+typedef struct {
+    int32_t epochs;     /* maximum number of epochs */
+    int32_t minibatch;  /* samples per Adam step */
+    int32_t patience;   /* epochs without a better validation loss before a member stops improving */
+    float lr, beta1, beta2, eps;  /* Adam */
+    float val_frac;     /* fraction held out for validation, in [0, 0.9) */
+    uint64_t seed;      /* split, bootstrap resamples and epoch order */
+} eor_train_cfg;
+
+/*
+ * Create an ensemble on HIP device `device` with He-normal weights (one
+ * seeded stream per member) and zero biases. lo, hi: host double [n_in],
+ * hi > lo, the prior box. Sizes: 1 <= n_in <= 1024, 1 <= n_members <= 64,
+ * 1 <= hidden <= 4096.
+ */
+eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int32_t hidden,
+                                uint64_t seed, const double *lo, const double *hi,
+                                eor_surrogate **out);
+void eor_surrogate_destroy(eor_surrogate *s);
+
+/* Parameters per member and number of members (either output may be NULL). */
+eor_status eor_surrogate_size(const eor_surrogate *s, int64_t *params_per_member,
+                              int32_t *n_members);
+
+/*
+ * Copy all parameters out (get: device float [n_members x P]) and/or replace
+ * them (set: same layout; also clears the Adam moments and step count).
+ */
+eor_status eor_surrogate_params(eor_surrogate *s, float *get, const float *set, void *stream);
+
+/* Get (host double [2]) and/or set the target standardisation (mean, std). */
+eor_status eor_surrogate_standardisation(eor_surrogate *s, double *get_mean_std,
+                                         const double *set_mean_std);
+
+/*
+ * Train on N exact evaluations: theta device double [N x n_in], logL device
+ * double [N] (finite). Each member trains on its own bootstrap resample of
+ * the training split with minibatch Adam; after every epoch the validation
+ * loss decides each member's best parameters, which are kept. Stops after
+ * cfg->epochs or when no member has improved for cfg->patience epochs.
+ * Synchronises the stream.
+ */
+eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta, const double *logL,
+                               const eor_train_cfg *cfg, void *stream);
+
+/* Epochs run by the last training and each member's best validation loss
+ * (host double [n_members], standardised units); either may be NULL. */
+eor_status eor_surrogate_report(const eor_surrogate *s, int32_t *epochs_run, double *val_loss);
+
+/*
+ * One training step's pieces, exposed for checking: the mean squared error
+ * of every member on its own batch (x: device float [n_members x nb x n_in],
+ * already scaled; y: device float [n_members x nb], standardised) and its
+ * gradient (loss: device float [n_members]; grad: device float
+ * [n_members x P]; either may be NULL), and one Adam update of all
+ * parameters from the last computed gradient.
+ */
+eor_status eor_surrogate_loss_grad(eor_surrogate *s, int64_t nb, const float *x, const float *y,
+                                   float *loss, float *grad, void *stream);
+eor_status eor_surrogate_adam_step(eor_surrogate *s, const eor_train_cfg *cfg, void *stream);
+
+/*
+ * Ensemble prediction for B points (theta device double [B x n_in]): mean
+ * and spread (device double [B], either may be NULL) in logL units, and
+ * optionally each member's standardised output (members: device float
+ * [n_members x B]).
+ */
+eor_status eor_surrogate_infer(eor_surrogate *s, int64_t B, const double *theta, double *mean,
+                               double *spread, float *members, void *stream);
+
+/*
+ * As eor_surrogate_infer, plus the gate: decision[b] (device int32 [B]) = 0
+ * (reject without an exact call) when spread <= tau and mean < L_min,
+ * otherwise 1 (evaluate exactly: the surrogate is unsure, or the point may
+ * be accepted and must be judged exactly).
+ */
+eor_status eor_surrogate_gate(eor_surrogate *s, int64_t B, const double *theta, double L_min,
+                              double tau, double *mean, double *spread, float *members,
+                              int32_t *decision, void *stream);
+
+/*
+ * Stable compaction: the rows s of rows (device double [n x n_cols]) with
+ * keep[s] != 0 are copied, in order, to rows_out (may be NULL), their
+ * indices to index_out (device int32, may be NULL), and their number to
+ * *count_out (device int32).
+ */
+eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, const double *rows,
+                            double *rows_out, int32_t *index_out, int32_t *count_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,18 @@ _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
 
 
+class TrainCfg(ctypes.Structure):
+    """eor_train_cfg."""
+    _fields_ = [("epochs", ctypes.c_int32), ("minibatch", ctypes.c_int32), ("patience", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("val_frac", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+def train_cfg(epochs=500, minibatch=1024, patience=20, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              val_frac=0.1, seed=0) -> TrainCfg:
+    return TrainCfg(epochs, minibatch, patience, lr, beta1, beta2, eps, val_frac, seed)
+
+
 class EorError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"eor status {status}: {msg}")
@@ -65,9 +77,27 @@ def lib() -> ctypes.CDLL:
         L.eor_group_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                                        ctypes.POINTER(_I64)]
         L.eor_autotune.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.c_char_p, _I32, _P]
+        L.eor_surrogate_create.argtypes = [ctypes.c_int, _I32, _I32, _I32, ctypes.c_uint64, _P, _P,
+                                           ctypes.POINTER(_P)]
+        L.eor_surrogate_destroy.argtypes = [_P]
+        L.eor_surrogate_destroy.restype = None
+        L.eor_surrogate_size.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]
+        L.eor_surrogate_params.argtypes = [_P, _P, _P, _P]
+        L.eor_surrogate_standardisation.argtypes = [_P, _P, _P]
+        L.eor_surrogate_train.argtypes = [_P, _I64, _P, _P, ctypes.POINTER(TrainCfg), _P]
+        L.eor_surrogate_report.argtypes = [_P, ctypes.POINTER(_I32), _P]
+        L.eor_surrogate_loss_grad.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
+        L.eor_surrogate_adam_step.argtypes = [_P, ctypes.POINTER(TrainCfg), _P]
+        L.eor_surrogate_infer.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
+        L.eor_surrogate_gate.argtypes = [_P, _I64, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
+        L.eor_compact_rows.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
                      "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
-                     "eor_group_set_graph", "eor_group_tuning", "eor_autotune"):
+                     "eor_group_set_graph", "eor_group_tuning", "eor_autotune", "eor_surrogate_create",
+                     "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
+                     "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
+                     "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
+                     "eor_compact_rows"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -237,6 +267,116 @@ class Group:
         cp = None if cache_path is None else str(cache_path).encode()
         check(lib().eor_autotune(self._h, B, tp, cp, 1 if force else 0, _stream(stream)))
         return self.tuning()[:2]
+
+
+class Surrogate:
+    """Ensemble of MLP surrogates of logL(theta) (FP32, trained on the GPU)."""
+
+    def __init__(self, n_in, lo, hi, n_members=5, hidden=256, seed=0, device=0):
+        lo = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, dtype=np.float64), (n_in,)))
+        hi = np.ascontiguousarray(np.broadcast_to(np.asarray(hi, dtype=np.float64), (n_in,)))
+        self._h = _P()
+        check(lib().eor_surrogate_create(int(device), int(n_in), int(n_members), int(hidden), int(seed),
+                                         lo.ctypes.data, hi.ctypes.data, ctypes.byref(self._h)))
+        self.n_in, self.M, self.H, self.device = int(n_in), int(n_members), int(hidden), device
+        P = _I64()
+        check(lib().eor_surrogate_size(self._h, ctypes.byref(P), None))
+        self.P = P.value
+
+    def close(self):
+        if self._h:
+            lib().eor_surrogate_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import torch
+        out = torch.empty((self.M, self.P), dtype=torch.float32, device=f"cuda:{self.device}")
+        check(lib().eor_surrogate_params(self._h, out.data_ptr(), None, _stream()))
+        return out
+
+    def set_params(self, p):
+        import torch
+        p = _dev(p, torch.float32).reshape(self.M, self.P).contiguous()
+        check(lib().eor_surrogate_params(self._h, None, p.data_ptr(), _stream()))
+
+    def standardisation(self, mean_std=None):
+        out = np.zeros(2)
+        st = None if mean_std is None else np.ascontiguousarray(mean_std, dtype=np.float64)
+        check(lib().eor_surrogate_standardisation(self._h, out.ctypes.data,
+                                                  None if st is None else st.ctypes.data))
+        return out if st is None else st
+
+    def train(self, theta, logL, cfg=None, stream=None):
+        import torch
+        theta = _dev(theta, torch.float64)
+        logL = _dev(logL, torch.float64)
+        cfg = cfg or train_cfg()
+        check(lib().eor_surrogate_train(self._h, theta.shape[0], theta.data_ptr(), logL.data_ptr(),
+                                        ctypes.byref(cfg), _stream(stream)))
+        ep = _I32()
+        val = np.zeros(self.M)
+        check(lib().eor_surrogate_report(self._h, ctypes.byref(ep), val.ctypes.data))
+        return ep.value, val
+
+    def loss_grad(self, x, y):
+        import torch
+        x = _dev(x, torch.float32)
+        y = _dev(y, torch.float32)
+        nb = y.shape[-1]
+        loss = torch.empty(self.M, dtype=torch.float32, device=x.device)
+        grad = torch.empty((self.M, self.P), dtype=torch.float32, device=x.device)
+        check(lib().eor_surrogate_loss_grad(self._h, nb, x.data_ptr(), y.data_ptr(), loss.data_ptr(),
+                                            grad.data_ptr(), _stream()))
+        return loss, grad
+
+    def adam_step(self, cfg):
+        check(lib().eor_surrogate_adam_step(self._h, ctypes.byref(cfg), _stream()))
+
+    def infer(self, theta, members=False):
+        import torch
+        theta = _dev(theta, torch.float64)
+        B = theta.shape[0]
+        mean = torch.empty(B, dtype=torch.float64, device=theta.device)
+        spread = torch.empty(B, dtype=torch.float64, device=theta.device)
+        mem = torch.empty((self.M, B), dtype=torch.float32, device=theta.device) if members else None
+        check(lib().eor_surrogate_infer(self._h, B, theta.data_ptr(), mean.data_ptr(), spread.data_ptr(),
+                                        None if mem is None else mem.data_ptr(), _stream()))
+        return (mean, spread, mem) if members else (mean, spread)
+
+    def gate(self, theta, L_min, tau):
+        """(mean, spread, decision): decision 1 = evaluate exactly, 0 = reject."""
+        import torch
+        theta = _dev(theta, torch.float64)
+        B = theta.shape[0]
+        mean = torch.empty(B, dtype=torch.float64, device=theta.device)
+        spread = torch.empty(B, dtype=torch.float64, device=theta.device)
+        dec = torch.empty(B, dtype=torch.int32, device=theta.device)
+        check(lib().eor_surrogate_gate(self._h, B, theta.data_ptr(), float(L_min), float(tau), mean.data_ptr(),
+                                       spread.data_ptr(), None, dec.data_ptr(), _stream()))
+        return mean, spread, dec
+
+
+def compact_rows(keep, rows=None):
+    """(rows_out, index_out, count) for the rows with keep != 0, in order."""
+    import torch
+    keep = _dev(keep, torch.int32)
+    n = keep.shape[0]
+    n_cols = 0 if rows is None else (rows.shape[1] if rows.dim() > 1 else 1)
+    if rows is not None:
+        rows = _dev(rows, torch.float64)
+    out = torch.empty((max(n, 1), max(n_cols, 1)), dtype=torch.float64, device=keep.device) if rows is not None else None
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=keep.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=keep.device)
+    check(lib().eor_compact_rows(n, n_cols, keep.data_ptr(), None if rows is None else rows.data_ptr(),
+                                 None if out is None else out.data_ptr(), idx.data_ptr(), cnt.data_ptr(), _stream()))
+    c = int(cnt.item())
+    return (None if out is None else out[:c]), idx[:c], c
 
 
 def version() -> str:
