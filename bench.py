@@ -177,6 +177,44 @@ def bench_group(args):
         c.close()
 
 
+def bench_gated(args):
+    """Nested sampling on the 12-bin n = 4096 dataset, once with every
+    proposal evaluated exactly and once gated by the surrogate ensemble
+    (same seed): throughput in proposals judged per second, exact calls
+    avoided, wall-clock speedup, and agreement of evidence and posterior."""
+    import torch
+    import synth
+    import paper_2501_12928_amd as eor
+    from paper_2501_12928_amd.sampler import run_plain_and_gated
+    inst = synth.gen(args.gated_config, n_theta=1)
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
+    sur = eor.Surrogate(inst.n_k, inst.lo, inst.hi, n_members=5, hidden=256, seed=1)
+    cfg = eor.train_cfg(epochs=args.train_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=5)
+    plain, gated, cmp = run_plain_and_gated(ctx, inst.n_k, inst.lo, inst.hi, sur, n_live=args.n_live, seed=7,
+                                            tau=args.tau, first_train=args.first_train,
+                                            retrain_every=args.retrain_every, window=args.window,
+                                            margin=args.margin, train_cfg=cfg, batch=512, dlogz=0.01,
+                                            audit_frac=0.01, pool_factor=args.pool_factor)
+    m, sd = gated.posterior_moments()
+    print(json.dumps({
+        "metric": "proposals judged per second by nested sampling at n=4096 complex FP64, surrogate-gated",
+        "value": gated.n_proposed / gated.wall_s, "unit": "proposals/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64 likelihood, f32 surrogate", "data": "synthetic",
+        "config": {"workload": f"T complex128 {inst.m}x{inst.n}, {inst.n_k} k-bins, n_live={args.n_live}, "
+                               f"gate tau={args.tau}, first training after {args.first_train} exact "
+                               f"evaluations, retrain every {args.retrain_every} iterations on the last "
+                               f"{args.window} within {args.margin} of the threshold, pools of "
+                               f"{args.pool_factor} x 512 proposals"},
+        "plain_proposals_per_s": plain.n_proposed / plain.wall_s,
+        "comparison": cmp,
+        "posterior_mean": m.tolist(), "posterior_std": sd.tolist(),
+        "theta_true": inst.theta_true.tolist()}))
+    sur.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,8 +222,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
-    ap.add_argument("--workload", choices=["metric", "group"], default="metric",
-                    help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances")
+    ap.add_argument("--workload", choices=["metric", "group", "gated"], default="metric",
+                    help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances; "
+                         "gated: nested sampling at 20000x4096 without and with the surrogate gate")
+    ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
+    ap.add_argument("--n-live", type=int, default=500)
+    ap.add_argument("--first-train", type=int, default=30000)
+    ap.add_argument("--retrain-every", type=int, default=2000)
+    ap.add_argument("--window", type=int, default=8000)
+    ap.add_argument("--tau", type=float, default=0.05)
+    ap.add_argument("--margin", type=float, default=10.0)
+    ap.add_argument("--train-epochs", type=int, default=400)
+    ap.add_argument("--train-minibatch", type=int, default=256)
+    ap.add_argument("--pool-factor", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -212,6 +261,8 @@ def main():
 
     if args.workload == "group":
         return bench_group(args)
+    if args.workload == "gated":
+        return bench_gated(args)
 
     inst = synth.gen(CONFIG_ID)
     B, n, m = inst.theta.shape[0], inst.n, inst.m

@@ -221,12 +221,17 @@ __global__ void colsum_kernel(const float *__restrict__ dZ, int64_t sHz, int H, 
     grad[z * P + off + k] = s;
 }
 
-// Adam with bias-corrected moments; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+// Adam with bias-corrected moments: step t = *step + 1 (the counter lives
+// in device memory so that a captured epoch can be replayed unchanged),
+// c1 = 1 - beta1^t, c2 = 1 - beta2^t.
 __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
-                            float c2) {
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            const int64_t *__restrict__ step) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
+    const double t = (double)(*step + 1);
+    const float c1 = (float)(1.0 - pow((double)b1, t));
+    const float c2 = (float)(1.0 - pow((double)b2, t));
     const float ge = g[e];
     const float me = b1 * m[e] + (1.0f - b1) * ge;
     const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
@@ -234,6 +239,8 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
     v[e] = ve;
     p[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
 }
+
+__global__ void tick_kernel(int64_t *step) { *step += 1; }
 
 // Ensemble statistics in logL units (FP64): mean and population spread of
 // y_mean + y_std f_m over the members; with a gate, decision 1 = evaluate
@@ -347,7 +354,11 @@ struct eor_surrogate {
     int32_t *d_counts = nullptr;
     int64_t counts_cap = 0;
     uint64_t seed = 0;
-    int64_t adam_t = 0;
+    int64_t *d_step = nullptr;      // Adam step count (device)
+    hipGraphExec_t epoch_exec = nullptr;  // one captured training epoch
+    hipGraph_t epoch_graph = nullptr;
+    int64_t epoch_key[4] = {0, 0, 0, 0};  // (steps, nb, row, n_tr) it was captured for
+    hipStream_t cap_stream = nullptr;
     int epochs_run = 0;
     std::vector<double> best_val;
 };
@@ -371,8 +382,18 @@ void dfree(T *&p) {
     p = nullptr;
 }
 
+void drop_epoch_graph(eor_surrogate &s) {
+    if (s.epoch_exec) (void)hipGraphExecDestroy(s.epoch_exec);
+    if (s.epoch_graph) (void)hipGraphDestroy(s.epoch_graph);
+    s.epoch_exec = nullptr;
+    s.epoch_graph = nullptr;
+    std::memset(s.epoch_key, 0, sizeof(s.epoch_key));
+}
+
+// (Re)allocating any buffer a captured epoch refers to drops that graph.
 hipError_t ensure_act(eor_surrogate &s, int64_t nb) {
     if (s.cap >= nb) return hipSuccess;
+    drop_epoch_graph(s);
     dfree(s.Xb); dfree(s.Yb); dfree(s.Z1); dfree(s.H1); dfree(s.Z2); dfree(s.H2);
     dfree(s.dZ); dfree(s.dH); dfree(s.f); dfree(s.dF);
     s.cap = 0;
@@ -458,13 +479,26 @@ void backward(eor_surrogate &s, int nb, hipStream_t st) {
 }
 
 void adam(eor_surrogate &s, const eor_train_cfg &cfg, hipStream_t st) {
-    ++s.adam_t;
-    const float c1 = (float)(1.0 - std::pow((double)cfg.beta1, (double)s.adam_t));
-    const float c2 = (float)(1.0 - std::pow((double)cfg.beta2, (double)s.adam_t));
     const int64_t n = (int64_t)s.M * s.P;
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.params, s.grad, s.mom,
-                       s.vel, n, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, c1, c2);
+                       s.vel, n, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, s.d_step);
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, s.d_step);
 }
+
+// All minibatch steps of one epoch (gather, forward, backward, Adam), for
+// capture into a graph: the indices of the epoch are refreshed in place
+// before every replay, and the Adam step count is read from device memory.
+void epoch_steps(eor_surrogate &s, const eor_train_cfg &cfg, int64_t steps, int nb, int64_t row,
+                 hipStream_t st) {
+    for (int64_t k = 0; k < steps; ++k) {
+        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nb * s.n_in + 255) / 256), (unsigned)s.M), dim3(256), 0,
+                           st, s.X, s.Y, s.n_in, s.idx + k * nb, row, nb, s.Xb, s.Yb);
+        forward(s, s.Xb, (int64_t)nb * s.n_in, nb, st);
+        backward(s, nb, st);
+        adam(s, cfg, st);
+    }
+}
+
 
 void he_init(eor_surrogate &s, std::vector<float> &h) {
     h.assign((size_t)s.M * s.P, 0.0f);
@@ -521,6 +555,8 @@ eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int
     if (e == hipSuccess) e = hipMalloc(&s->mom, pb);
     if (e == hipSuccess) e = hipMalloc(&s->vel, pb);
     if (e == hipSuccess) e = hipMalloc(&s->loss, (size_t)s->M * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&s->d_step, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMemset(s->d_step, 0, sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_lo, n_in * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&s->d_hi, n_in * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(s->d_lo, lo, n_in * sizeof(double), hipMemcpyHostToDevice);
@@ -546,7 +582,9 @@ void eor_surrogate_destroy(eor_surrogate *s) {
     dfree(s->d_lo); dfree(s->d_hi);
     dfree(s->Xb); dfree(s->Yb); dfree(s->Z1); dfree(s->H1); dfree(s->Z2); dfree(s->H2);
     dfree(s->dZ); dfree(s->dH); dfree(s->f); dfree(s->dF);
-    dfree(s->X); dfree(s->Y); dfree(s->idx); dfree(s->d_counts);
+    dfree(s->X); dfree(s->Y); dfree(s->idx); dfree(s->d_counts); dfree(s->d_step);
+    drop_epoch_graph(*s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }
 
@@ -569,7 +607,7 @@ eor_status eor_surrogate_params(eor_surrogate *s, float *get, const float *set, 
         e = hipMemcpyAsync(s->params, set, pb, hipMemcpyDeviceToDevice, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->mom, 0, pb, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->vel, 0, pb, hs);
-        s->adam_t = 0;
+        if (e == hipSuccess) e = hipMemsetAsync(s->d_step, 0, sizeof(int64_t), hs);
     }
     if (e == hipSuccess && get) e = hipMemcpyAsync(get, s->params, pb, hipMemcpyDeviceToDevice, hs);
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_params");
@@ -651,6 +689,7 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
     s->ymean = mu;
     s->ystd = sd;
     if (s->data_cap < N) {
+        drop_epoch_graph(*s);
         dfree(s->X);
         dfree(s->Y);
         s->data_cap = 0;
@@ -678,6 +717,7 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
     // one row of indices per member: an epoch's shuffled bootstrap sample, then the validation set
     const int64_t row = n_tr + n_val;
     if (s->idx_cap < s->M * row) {
+        drop_epoch_graph(*s);
         dfree(s->idx);
         s->idx_cap = 0;
         e = hipMalloc(&s->idx, (size_t)s->M * row * sizeof(int32_t));
@@ -702,12 +742,30 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
         }
         e = hipMemcpyAsync(s->idx, hidx.data(), hidx.size() * sizeof(int32_t), hipMemcpyHostToDevice, hs);
         if (e != hipSuccess) return eor::hip_status(e, "indices");
-        for (int64_t k = 0; k < steps; ++k) {
-            hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nb * s->n_in + 255) / 256), (unsigned)s->M), dim3(256),
-                               0, hs, s->X, s->Y, s->n_in, s->idx + k * nb, row, nb, s->Xb, s->Yb);
-            forward(*s, s->Xb, (int64_t)nb * s->n_in, nb, hs);
-            backward(*s, nb, hs);
-            adam(*s, *cfg, hs);
+        const int64_t key[4] = {steps, nb, row, n_tr};
+        if (!s->epoch_exec || std::memcmp(key, s->epoch_key, sizeof(key)) != 0) {
+            drop_epoch_graph(*s);
+            if (!s->cap_stream) {
+                e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return eor::hip_status(e, "capture stream");
+            }
+            e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return eor::hip_status(e, "hipStreamBeginCapture");
+            epoch_steps(*s, *cfg, steps, nb, row, s->cap_stream);
+            e = hipStreamEndCapture(s->cap_stream, &s->epoch_graph);
+            if (e == hipSuccess) e = hipGraphInstantiate(&s->epoch_exec, s->epoch_graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_epoch_graph(*s);
+                return eor::hip_status(e, "epoch graph");
+            }
+            std::memcpy(s->epoch_key, key, sizeof(key));
+        }
+        e = hipGraphLaunch(s->epoch_exec, hs);
+        if (e != hipSuccess) return eor::hip_status(e, "epoch replay");
+        // hidx is overwritten for the next epoch only after this epoch ran
+        if (n_val == 0) {
+            e = hipStreamSynchronize(hs);
+            if (e != hipSuccess) return eor::hip_status(e, "epoch");
         }
         if (n_val == 0) continue;
         // validation loss of every member

@@ -1,0 +1,357 @@
+"""Nested sampling over the power-spectrum parameters, with batched
+proposals and an optional surrogate gate.
+
+The sampler plays the role the paper gives MultiNest (Summary: posterior
+samples and the Bayesian evidence for model selection): Skilling's nested
+sampling with n_live live points, replacements drawn uniformly from the
+prior box restricted to an enlarged bounding ellipsoid of the live points
+(single-ellipsoid rejection sampling, Mukherjee, Parkinson & Liddle 2006),
+and the evidence accumulated as Z = sum_i L_i (X_{i-1} - X_i) with
+X_i = exp(-i / n_live).
+
+Proposals are drawn and evaluated in batches (the GPU likelihood wants
+hundreds of theta per call) and consumed in order. A proposal evaluated
+against an older, lower threshold remains a valid replacement later: a
+point uniform in {L > L_old}, conditioned on L > L_new >= L_old, is uniform
+in {L > L_new}. The price is that the threshold rises while a batch is
+consumed, so many exactly evaluated proposals end up below it.
+
+With a gate (see GatedLikelihood), the surrogate's ensemble mean and
+spread are computed for a whole pool of proposals, and each proposal is
+judged when its turn comes, against the threshold of that moment: a
+proposal the surrogate is confident lies below it (spread <= tau and
+mean < L_min) is rejected without an exact evaluation; the uncertain ones
+are evaluated exactly, a batch of them at a time. Only exact values ever
+enter the live set, so every accepted point carries its exact FP64 logL. A
+small random fraction of the surrogate's rejections is evaluated anyway to
+measure false rejections.
+
+The bookkeeping is host logic in numpy; the likelihood, the surrogate and
+the compaction of proposals run in the library's kernels.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Result:
+    logz: float
+    logz_err: float
+    information: float
+    samples: np.ndarray        # dead points then the final live points
+    logl: np.ndarray
+    logw: np.ndarray           # log posterior weights (normalised)
+    iterations: int
+    n_exact: int               # exact likelihood evaluations
+    n_proposed: int            # proposals drawn inside the prior box
+    n_gate_rejected: int       # proposals rejected by the surrogate without an exact call
+    n_audited: int             # surrogate rejections evaluated anyway
+    n_false_reject: int        # ... of which the exact logL was above the threshold
+    n_retrain: int
+    wall_s: float
+    t_exact_s: float
+    t_gate_s: float
+    t_train_s: float
+
+    def posterior_moments(self):
+        w = np.exp(self.logw - self.logw.max())
+        w /= w.sum()
+        mean = w @ self.samples
+        var = w @ (self.samples - mean) ** 2
+        return mean, np.sqrt(var)
+
+
+def _logsubexp(a, b):
+    """log(exp(a) - exp(b)) for a > b."""
+    return a + math.log1p(-math.exp(b - a))
+
+
+class Ellipsoid:
+    """Bounding ellipsoid of a point set, enlarged by a volume factor."""
+
+    def __init__(self, pts: np.ndarray, enlarge: float):
+        d = pts.shape[1]
+        self.mu = pts.mean(axis=0)
+        C = np.cov(pts, rowvar=False).reshape(d, d) + 1e-12 * np.eye(d)
+        Ci = np.linalg.inv(C)
+        dx = pts - self.mu
+        k = float(np.max(np.einsum("ij,jk,ik->i", dx, Ci, dx)))
+        self.L = np.linalg.cholesky(C * k * enlarge ** (2.0 / d))
+
+    def sample(self, rng: np.random.Generator, n: int) -> np.ndarray:
+        d = self.mu.size
+        g = rng.standard_normal((n, d))
+        g /= np.linalg.norm(g, axis=1, keepdims=True)
+        r = rng.uniform(size=(n, 1)) ** (1.0 / d)
+        return self.mu + (g * r) @ self.L.T
+
+
+class NestedSampler:
+    """loglike(theta [B, d] float64) -> logL [B]; gate (optional) is a
+    GatedLikelihood-like object with predict(theta) -> (mean, spread) or
+    None, tau, trained, observe(theta, logL) and maybe_retrain(iteration)."""
+
+    def __init__(self, loglike, n_dim, lo, hi, n_live=500, enlarge=1.5, dlogz=0.01, batch=512,
+                 seed=0, gate=None, audit_frac=0.01, max_iter=2_000_000, pool_factor=1):
+        self.loglike = loglike
+        self.d = int(n_dim)
+        self.lo = np.broadcast_to(np.asarray(lo, dtype=np.float64), (self.d,)).copy()
+        self.hi = np.broadcast_to(np.asarray(hi, dtype=np.float64), (self.d,)).copy()
+        self.n_live = int(n_live)
+        self.enlarge = float(enlarge)
+        self.dlogz = float(dlogz)
+        self.batch = int(batch)
+        self.rng = np.random.default_rng(seed)
+        self.audit_rng = np.random.default_rng([seed, 1])
+        self.gate = gate
+        self.audit_frac = float(audit_frac)
+        self.max_iter = int(max_iter)
+        self.pool_factor = int(pool_factor)
+        self.stats = dict(n_exact=0, n_proposed=0, n_gate_rejected=0, n_audited=0, n_false_reject=0,
+                          t_exact=0.0, t_gate=0.0)
+
+    def _exact(self, th):
+        t0 = time.perf_counter()
+        L = np.asarray(self.loglike(th), dtype=np.float64)
+        self.stats["t_exact"] += time.perf_counter() - t0
+        self.stats["n_exact"] += th.shape[0]
+        if self.gate is not None:
+            self.gate.observe(th, L)
+        return L
+
+    def _propose(self, live):
+        """A pool of proposals inside the prior box from the live points'
+        enlarged bounding ellipsoid: one exact batch without a trained gate,
+        pool_factor batches with one (the surrogate screens them cheaply)."""
+        ell = Ellipsoid(live, self.enlarge)
+        out = []
+        gated = self.gate is not None and self.gate.trained
+        need = self.batch * (self.pool_factor if gated else 1)
+        while need > 0:
+            x = ell.sample(self.rng, max(need * 2, 64))
+            x = x[np.all((x >= self.lo) & (x <= self.hi), axis=1)]
+            out.append(x[:need])
+            need -= out[-1].shape[0]
+        return np.concatenate(out)
+
+    def _new_pool(self, live):
+        """A pool of proposals: exact logL evaluated now (no gate, or an
+        untrained one) or left for later (NaN) with the surrogate's mean and
+        spread attached."""
+        th = self._propose(live)
+        self.stats["n_proposed"] += th.shape[0]
+        pool = {"th": th, "L": np.full(th.shape[0], np.nan), "mean": None, "spread": None, "pos": 0}
+        pred = None
+        if self.gate is not None:
+            t0 = time.perf_counter()
+            pred = self.gate.predict(th)
+            self.stats["t_gate"] += time.perf_counter() - t0
+        if pred is None:
+            pool["L"][:] = self._exact(th)
+        else:
+            pool["mean"], pool["spread"] = pred
+        return pool
+
+    def _confident_reject(self, pool, i, L_min):
+        return (pool["mean"] is not None and pool["spread"][i] <= self.gate.tau
+                and pool["mean"][i] < L_min)
+
+    def _next_valid(self, pool, L_min):
+        """Index of the next proposal of the pool with exact logL > L_min,
+        or None when the pool is used up."""
+        th, L = pool["th"], pool["L"]
+        while pool["pos"] < th.shape[0]:
+            i = pool["pos"]
+            if not np.isnan(L[i]):
+                pool["pos"] += 1
+                if L[i] > L_min:
+                    return i
+                continue
+            if self._confident_reject(pool, i, L_min):
+                L[i] = -np.inf
+                pool["pos"] += 1
+                self.stats["n_gate_rejected"] += 1
+                if self.audit_frac > 0 and self.audit_rng.uniform() < self.audit_frac:
+                    La = float(self._exact(th[i:i + 1])[0])
+                    self.stats["n_audited"] += 1
+                    self.stats["n_false_reject"] += int(La > L_min)
+                continue
+            # evaluate exactly the next batch of proposals the gate is unsure of
+            idx = [j for j in range(i, th.shape[0])
+                   if np.isnan(L[j]) and not self._confident_reject(pool, j, L_min)][:self.batch]
+            L[idx] = self._exact(th[idx])
+        return None
+
+    def run(self) -> Result:
+        t_start = time.perf_counter()
+        d, n = self.d, self.n_live
+        live = self.lo + (self.hi - self.lo) * self.rng.uniform(size=(n, d))
+        live_L = self._exact(live)
+        dead, dead_L, dead_lnw = [], [], []
+        logz = -np.inf
+        ln_x_prev = 0.0
+        pool = None
+        it = 0
+        t_train0 = self.gate.train_seconds if self.gate is not None else 0.0
+        while it < self.max_iter:
+            worst = int(np.argmin(live_L))
+            L_min = float(live_L[worst])
+            ln_x = -(it + 1) / n
+            ln_w = L_min + _logsubexp(ln_x_prev, ln_x)
+            logz = np.logaddexp(logz, ln_w)
+            dead.append(live[worst].copy())
+            dead_L.append(L_min)
+            dead_lnw.append(ln_w)
+            ln_x_prev = ln_x
+            it += 1
+            # replacement: the next pooled proposal above the threshold
+            j = None if pool is None else self._next_valid(pool, L_min)
+            while j is None:
+                pool = self._new_pool(live)
+                j = self._next_valid(pool, L_min)
+            live[worst] = pool["th"][j]
+            live_L[worst] = pool["L"][j]
+            if self.gate is not None:
+                self.gate.maybe_retrain(it)
+            # stop when the live points can no longer change ln Z by dlogz
+            if np.logaddexp(logz, float(np.max(live_L)) + ln_x) - logz < self.dlogz:
+                break
+        # the final live points share the remaining prior volume
+        ln_wl = live_L + ln_x_prev - math.log(n)
+        logz_final = np.logaddexp(logz, np.logaddexp.reduce(ln_wl))
+        samples = np.concatenate([np.array(dead), live])
+        logl = np.concatenate([np.array(dead_L), live_L])
+        lnw = np.concatenate([np.array(dead_lnw), ln_wl])
+        # information H = sum_i p_i ln(L_i / Z), live points included
+        p = np.exp(lnw - logz_final)
+        H = float(np.sum(p * (logl - logz_final)))
+        st = self.stats
+        return Result(logz=float(logz_final), logz_err=math.sqrt(max(H, 0.0) / n), information=H,
+                      samples=samples, logl=logl, logw=lnw - logz_final, iterations=it,
+                      n_exact=st["n_exact"], n_proposed=st["n_proposed"],
+                      n_gate_rejected=st["n_gate_rejected"], n_audited=st["n_audited"],
+                      n_false_reject=st["n_false_reject"],
+                      n_retrain=self.gate.n_train if self.gate is not None else 0,
+                      wall_s=time.perf_counter() - t_start, t_exact_s=st["t_exact"], t_gate_s=st["t_gate"],
+                      t_train_s=(self.gate.train_seconds - t_train0) if self.gate is not None else 0.0)
+
+
+class GatedLikelihood:
+    """The surrogate gate for NestedSampler: keeps the exact evaluations it
+    sees, (re)trains the surrogate on the most recent ones near the current
+    threshold, and decides which proposals need an exact call. Until the
+    first training every proposal is evaluated exactly.
+
+    Nested-sampling rejections lie just below the threshold L_min (the
+    proposals come from a tight ellipsoid around the live points), so the
+    surrogate must be accurate there: retraining uses the last `window`
+    exact evaluations with logL >= L_min - margin, standardised on that
+    window, starting from the previous parameters.
+
+    surrogate: an object with train(theta, logL, ...) and gate(theta, L_min,
+    tau) -> (mean, spread, decision) (paper_2501_12928_amd.Surrogate, or any
+    stand-in with that interface)."""
+
+    def __init__(self, surrogate, tau=0.05, first_train=100_000, retrain_every=0, window=100_000,
+                 margin=np.inf, train_kwargs=None):
+        self.s = surrogate
+        self.tau = float(tau)
+        self.first_train = int(first_train)
+        self.retrain_every = int(retrain_every)
+        self.window = int(window)
+        self.margin = float(margin)
+        self.train_kwargs = train_kwargs or {}
+        self._th = []
+        self._L = []
+        self._count = 0
+        self.trained = False
+        self.n_train = 0
+        self.train_seconds = 0.0
+        self._last_iter = 0
+        self.L_min = -np.inf
+
+    def observe(self, th, L):
+        if L.size:
+            self.L_min = max(self.L_min, float(np.min(L)))
+        ok = np.isfinite(L)
+        self._th.append(np.asarray(th)[ok])
+        self._L.append(np.asarray(L)[ok])
+        self._count += int(ok.sum())
+        if not self.trained and self._count >= self.first_train:
+            self._train()
+
+    def _train(self):
+        th = np.concatenate(self._th)
+        L = np.concatenate(self._L)
+        keep = max(self.window * 4, 1)
+        th, L = th[-keep:], L[-keep:]           # bounded history
+        self._th, self._L = [th], [L]
+        near = L >= self.L_min - self.margin
+        if np.count_nonzero(near) >= 256:
+            th, L = th[near], L[near]
+        th, L = th[-self.window:], L[-self.window:]
+        t0 = time.perf_counter()
+        self.s.train(th, L, **self.train_kwargs)
+        self.train_seconds += time.perf_counter() - t0
+        self.trained = True
+        self.n_train += 1
+
+    def maybe_retrain(self, it):
+        if self.trained and self.retrain_every > 0 and it - self._last_iter >= self.retrain_every:
+            self._last_iter = it
+            self._train()
+
+    def predict(self, th):
+        """(mean, spread) of the ensemble for a pool of proposals, or None
+        before the first training."""
+        if not self.trained:
+            return None
+        m, sp, _ = self.s.gate(th, -np.inf, self.tau)
+        as_np = (lambda x: x.cpu().numpy()) if hasattr(m, "cpu") else np.asarray
+        return as_np(m), as_np(sp)
+
+
+def exact_gpu(ctx):
+    """loglike(theta numpy [B, d]) -> numpy [B] through eor_loglike_batch."""
+    import torch
+
+    def f(th):
+        L, _ = ctx.loglike_batch(torch.from_numpy(np.ascontiguousarray(th)).cuda())
+        return L.cpu().numpy()
+    return f
+
+
+def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0.05, first_train=100_000,
+                        retrain_every=0, window=100_000, margin=np.inf, train_cfg=None, batch=512, dlogz=0.01,
+                        audit_frac=0.01, pool_factor=1):
+    """The same nested-sampling run without and with the surrogate gate
+    (same seed), and the comparison: evidence, per-bin posterior mean and
+    standard deviation, exact calls avoided and wall-clock speedup."""
+    loglike = exact_gpu(ctx)
+    plain = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed).run()
+    gate = GatedLikelihood(surrogate, tau=tau, first_train=first_train, retrain_every=retrain_every,
+                           window=window, margin=margin,
+                           train_kwargs={"cfg": train_cfg} if train_cfg is not None else {})
+    gated = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
+                          gate=gate, audit_frac=audit_frac, pool_factor=pool_factor).run()
+    m1, s1 = plain.posterior_moments()
+    m2, s2 = gated.posterior_moments()
+    return plain, gated, {
+        "logz_plain": plain.logz, "logz_gated": gated.logz,
+        "logz_tolerance": 3.0 * math.sqrt(plain.information / n_live),
+        "max_dmean_over_sigma": float(np.max(np.abs(m1 - m2) / s1)),
+        "max_dstd_rel": float(np.max(np.abs(s2 / s1 - 1.0))),
+        "exact_calls_plain": plain.n_exact, "exact_calls_gated": gated.n_exact,
+        "exact_calls_avoided_frac": 1.0 - gated.n_exact / plain.n_exact,
+        "gate_rejected": gated.n_gate_rejected, "audited": gated.n_audited,
+        "false_rejections": gated.n_false_reject,
+        "wall_plain_s": plain.wall_s, "wall_gated_s": gated.wall_s,
+        "speedup": plain.wall_s / gated.wall_s,
+        "train_s": gated.t_train_s, "gate_s": gated.t_gate_s, "retrains": gated.n_retrain,
+        "iterations_plain": plain.iterations, "iterations_gated": gated.iterations,
+    }

@@ -1,0 +1,109 @@
+"""Nested sampler (host logic) on closed-form problems: a Gaussian in a
+uniform box has an analytic evidence; gating with a perfect surrogate must
+keep the answer while avoiding exact calls; a gate that never rejects must
+reproduce the ungated run exactly."""
+import math
+
+import numpy as np
+from scipy.special import erf
+
+from paper_2501_12928_amd.sampler import Ellipsoid, GatedLikelihood, NestedSampler
+
+MU = np.array([0.3, -0.2, 1.0, 0.5])
+SIG = 0.5
+LO, HI = -5.0, 5.0
+
+
+def gauss_loglike(th):
+    th = np.atleast_2d(th)
+    d = th.shape[1]
+    return -0.5 * np.sum((th - MU[:d]) ** 2, axis=1) / SIG ** 2 - 0.5 * d * math.log(2 * math.pi * SIG ** 2)
+
+
+def gauss_logz(d):
+    """ln Z = ln( prod_k P(LO < x_k < HI) / (HI - LO)^d ) for the unit-mass Gaussian."""
+    mass = 1.0
+    for k in range(d):
+        a = (LO - MU[k]) / (SIG * math.sqrt(2))
+        b = (HI - MU[k]) / (SIG * math.sqrt(2))
+        mass *= 0.5 * (erf(b) - erf(a))
+    return math.log(mass) - d * math.log(HI - LO)
+
+
+class PerfectSurrogate:
+    """Stand-in with the surrogate interface: exact mean, zero spread."""
+
+    def __init__(self, spread=0.0):
+        self.spread = spread
+        self.trained_on = 0
+
+    def train(self, th, L):
+        self.trained_on = th.shape[0]
+
+    def gate(self, th, L_min, tau):
+        m = gauss_loglike(th)
+        s = np.full(th.shape[0], self.spread)
+        dec = np.where((s <= tau) & (m < L_min), 0, 1).astype(np.int32)
+        return m, s, dec
+
+
+def test_gaussian_evidence_and_posterior():
+    d = 4
+    ns = NestedSampler(gauss_loglike, d, LO, HI, n_live=300, dlogz=0.01, batch=256, seed=1)
+    r = ns.run()
+    truth = gauss_logz(d)
+    assert abs(r.logz - truth) < 4 * r.logz_err + 0.02, (r.logz, truth, r.logz_err)
+    mean, std = r.posterior_moments()
+    assert np.all(np.abs(mean - MU) < 0.05)
+    assert np.all(np.abs(std / SIG - 1) < 0.12)
+    # information of a Gaussian in a wide box: H = ln(V / (2 pi e sigma^2)^(d/2)) approx.
+    H_true = d * math.log(HI - LO) - 0.5 * d * math.log(2 * math.pi * math.e * SIG ** 2)
+    assert abs(r.information - H_true) < 0.3
+
+
+def test_gated_perfect_surrogate_keeps_answer_with_fewer_exact_calls():
+    d = 4
+    plain = NestedSampler(gauss_loglike, d, LO, HI, n_live=300, dlogz=0.01, batch=256, seed=2).run()
+    gate = GatedLikelihood(PerfectSurrogate(), tau=0.05, first_train=2000)
+    gated = NestedSampler(gauss_loglike, d, LO, HI, n_live=300, dlogz=0.01, batch=256, seed=2,
+                          gate=gate, audit_frac=0.05).run()
+    assert gate.n_train == 1
+    assert abs(gated.logz - plain.logz) < 3 * math.sqrt(plain.logz_err ** 2 + gated.logz_err ** 2)
+    m1, s1 = plain.posterior_moments()
+    m2, s2 = gated.posterior_moments()
+    assert np.all(np.abs(m1 - m2) < 0.15 * s1)
+    assert gated.n_gate_rejected > 0 and gated.n_false_reject == 0 and gated.n_audited > 0
+    assert gated.n_exact < 0.8 * plain.n_exact
+    # every accepted sample carries its exact logL
+    np.testing.assert_array_equal(gated.logl, gauss_loglike(gated.samples))
+
+
+def test_gate_that_never_rejects_reproduces_plain_run():
+    """With pools of one exact batch, a gate that is never confident leaves
+    every decision to the exact likelihood: the run is the plain run."""
+    d = 3
+    plain = NestedSampler(gauss_loglike, d, LO, HI, n_live=100, dlogz=0.05, batch=128, seed=3).run()
+    gate = GatedLikelihood(PerfectSurrogate(spread=1.0), tau=0.05, first_train=500)
+    gated = NestedSampler(gauss_loglike, d, LO, HI, n_live=100, dlogz=0.05, batch=128, seed=3, gate=gate,
+                          pool_factor=1).run()
+    assert gated.n_gate_rejected == 0
+    assert gated.logz == plain.logz
+    np.testing.assert_array_equal(gated.samples, plain.samples)
+
+
+def test_ellipsoid_bounds_and_volume():
+    rng = np.random.default_rng(4)
+    pts = rng.standard_normal((400, 3)) @ np.array([[1.0, 0.2, 0], [0, 0.5, 0.1], [0, 0, 2.0]])
+    ell = Ellipsoid(pts, 1.5)
+    Li = np.linalg.inv(ell.L)
+    r = np.linalg.norm((pts - ell.mu) @ Li.T, axis=1)
+    assert np.all(r <= 1.0 + 1e-9)
+    # the enlarged ellipsoid's volume is 1.5 times the tight one's
+    tight = Ellipsoid(pts, 1.0)
+    ratio = abs(np.linalg.det(ell.L) / np.linalg.det(tight.L))
+    assert abs(ratio - 1.5) < 1e-9
+    x = ell.sample(rng, 20000)
+    rx = np.linalg.norm((x - ell.mu) @ Li.T, axis=1)
+    assert np.all(rx <= 1.0 + 1e-9)
+    # uniform in the ball: P(r < 0.5) = 0.5^3
+    assert abs(np.mean(rx < 0.5) - 0.125) < 0.01
