@@ -196,7 +196,7 @@ def bench_gated(args):
                                             tau=args.tau, first_train=args.first_train,
                                             retrain_every=args.retrain_every, window=args.window,
                                             margin=args.margin, train_cfg=cfg, batch=512, dlogz=0.01,
-                                            audit_frac=0.01, pool_factor=args.pool_factor)
+                                            audit_frac=0.01, pool_factor=args.pool_factor, progress=2000)
     m, sd = gated.posterior_moments()
     print(json.dumps({
         "metric": "proposals judged per second by nested sampling at n=4096 complex FP64, surrogate-gated",

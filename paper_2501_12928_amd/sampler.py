@@ -97,7 +97,7 @@ class NestedSampler:
     None, tau, trained, observe(theta, logL) and maybe_retrain(iteration)."""
 
     def __init__(self, loglike, n_dim, lo, hi, n_live=500, enlarge=1.5, dlogz=0.01, batch=512,
-                 seed=0, gate=None, audit_frac=0.01, max_iter=2_000_000, pool_factor=1):
+                 seed=0, gate=None, audit_frac=0.01, max_iter=2_000_000, pool_factor=1, progress=0):
         self.loglike = loglike
         self.d = int(n_dim)
         self.lo = np.broadcast_to(np.asarray(lo, dtype=np.float64), (self.d,)).copy()
@@ -112,6 +112,7 @@ class NestedSampler:
         self.audit_frac = float(audit_frac)
         self.max_iter = int(max_iter)
         self.pool_factor = int(pool_factor)
+        self.progress = int(progress)
         self.stats = dict(n_exact=0, n_proposed=0, n_gate_rejected=0, n_audited=0, n_false_reject=0,
                           t_exact=0.0, t_gate=0.0)
 
@@ -218,6 +219,11 @@ class NestedSampler:
             live_L[worst] = pool["L"][j]
             if self.gate is not None:
                 self.gate.maybe_retrain(it)
+            if self.progress and it % self.progress == 0:
+                import sys
+                print(f"ns: iteration {it} ln Z {logz:.3f} L_min {L_min:.3f} exact {self.stats['n_exact']} "
+                      f"gate-rejected {self.stats['n_gate_rejected']} {time.perf_counter() - t_start:.1f}s",
+                      file=sys.stderr, flush=True)
             # stop when the live points can no longer change ln Z by dlogz
             if np.logaddexp(logz, float(np.max(live_L)) + ln_x) - logz < self.dlogz:
                 break
@@ -328,17 +334,18 @@ def exact_gpu(ctx):
 
 def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0.05, first_train=100_000,
                         retrain_every=0, window=100_000, margin=np.inf, train_cfg=None, batch=512, dlogz=0.01,
-                        audit_frac=0.01, pool_factor=1):
+                        audit_frac=0.01, pool_factor=1, progress=0):
     """The same nested-sampling run without and with the surrogate gate
     (same seed), and the comparison: evidence, per-bin posterior mean and
     standard deviation, exact calls avoided and wall-clock speedup."""
     loglike = exact_gpu(ctx)
-    plain = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed).run()
+    plain = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
+                          progress=progress).run()
     gate = GatedLikelihood(surrogate, tau=tau, first_train=first_train, retrain_every=retrain_every,
                            window=window, margin=margin,
                            train_kwargs={"cfg": train_cfg} if train_cfg is not None else {})
     gated = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
-                          gate=gate, audit_frac=audit_frac, pool_factor=pool_factor).run()
+                          gate=gate, audit_frac=audit_frac, pool_factor=pool_factor, progress=progress).run()
     m1, s1 = plain.posterior_moments()
     m2, s2 = gated.posterior_moments()
     return plain, gated, {
