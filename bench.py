@@ -141,7 +141,7 @@ def bench_group(args):
         ns.append(inst.n)
     g = eor.Group(ctxs)
     cache = os.environ.get("EOR_TUNE_CACHE", os.path.join("/tmp", "eor_tune.json"))
-    stages, wg = g.autotune(thetas, cache_path=cache, force=True)
+    stages, wg, tiles = g.autotune(thetas, cache_path=cache, force=True)
     outs, infos = g.loglike(thetas)
     for _ in range(args.warmup):
         outs, infos = g.loglike(thetas, outs=outs, infos=infos)
@@ -170,7 +170,7 @@ def bench_group(args):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "likelihood_kernel",
                      "launch_ms": ms, "flops_per_launch": flops},
-        "tuning": {"stages": stages, "wg_per_cu": wg, "graph": list(g.tuning()[2:])},
+        "tuning": {"stages": stages, "wg_per_cu": wg, "tiles_per_pass": tiles, "graph": list(g.tuning()[3:])},
         "precompute_s_total": t_pre, "all_info_zero": ok}))
     g.close()
     for c in ctxs:
@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=400)
     ap.add_argument("--train-minibatch", type=int, default=256)
     ap.add_argument("--pool-factor", type=int, default=1)
+    ap.add_argument("--tuning", default=None,
+                    help="launch choices 'stages,wg_per_cu,tiles_per_pass' of the likelihood batch "
+                         "(default: the library's)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -273,6 +276,8 @@ def main():
     logL = torch.empty(B, dtype=torch.float64, device="cuda")
     info = torch.empty(B, dtype=torch.int32, device="cuda")
     ctx = eor.Context(0)
+    if args.tuning:
+        ctx.set_tuning(*[int(v) for v in args.tuning.split(",")])
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
@@ -326,6 +331,7 @@ def main():
                      "kernel": "likelihood_kernel", "launch_ms": like_ms,
                      "flops_per_launch": fl},
         "loglike_evals_per_s": B / (like_ms / 1e3),
+        "tuning": dict(zip(("stages", "wg_per_cu", "tiles_per_pass"), ctx.tuning())),
         "gated": None,
     }
     if not args.no_precision:

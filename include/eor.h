@@ -140,6 +140,20 @@ eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *d
 eor_status eor_shape(const eor_ctx *ctx, int64_t *m, int64_t *n, int32_t *n_k);
 
 /*
+ * Launch choices of this context's eor_loglike_batch / eor_loglike_terms
+ * (execution parameters only; results do not depend on them beyond the
+ * summation order of the tile updates, which is the same for all):
+ *   stages          k-steps of 4 columns the panel update prefetches (2 or 4)
+ *   wg_per_cu       theta in flight per compute unit (1 or 2)
+ *   tiles_per_pass  tiles of a column updated per pass over its panel: 1
+ *                   (workgroups of 4 waves), or 2 (workgroups of 8 waves,
+ *                   which then need wg_per_cu = 1)
+ * Default: 4, 1, 2. Errors: EOR_ERR_ARG for any other combination.
+ */
+eor_status eor_set_tuning(eor_ctx *ctx, int32_t stages, int32_t wg_per_cu, int32_t tiles_per_pass);
+eor_status eor_get_tuning(const eor_ctx *ctx, int32_t *stages, int32_t *wg_per_cu, int32_t *tiles_per_pass);
+
+/*
  * Groups: many datasets of uneven size (e.g. independent frequency
  * sub-bands, each with its own T, noise, data and bins) evaluated together.
  * One eor_group_loglike call is one persistent launch: a fixed set of
@@ -174,15 +188,20 @@ eor_status eor_group_loglike(eor_group *g, const int64_t *B, const double *const
 /* Enable (default) or disable graph capture and replay for this group. */
 eor_status eor_group_set_graph(eor_group *g, int32_t enable);
 
+/* Set the group's launch choices (meaning and limits as eor_set_tuning). */
+eor_status eor_group_set_tuning(eor_group *g, int32_t stages, int32_t wg_per_cu, int32_t tiles_per_pass);
+
 /* Current launch choices of the group, and how many times it launched a
  * graph and captured one so far (any output may be NULL). */
 eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per_cu,
-                            int64_t *graph_launches, int64_t *graph_captures);
+                            int32_t *tiles_per_pass, int64_t *graph_launches,
+                            int64_t *graph_captures);
 
 /*
  * Autotuner: times the group on the given batch (same arguments as
  * eor_group_loglike, outputs discarded) for every candidate launch (panel
- * prefetch depth 2 or 4 k-steps x 1 or 2 theta in flight per CU) and keeps
+ * prefetch depth 2 or 4 k-steps x {1 tile per pass with 1 or 2 theta in
+ * flight per CU, 2 tiles per pass with 1}) and keeps
  * the fastest. With cache_path (may be NULL), the choice is stored in a JSON
  * file keyed by "<gfx arch>|<size bucket of the largest n: n<=512, n<=1024,
  * n<=2048, n<=4096, n>4096>|<single or group>", and an existing entry is

@@ -74,8 +74,11 @@ def lib() -> ctypes.CDLL:
         L.eor_group_loglike.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                         ctypes.POINTER(_P), _P]
         L.eor_group_set_graph.argtypes = [_P, _I32]
-        L.eor_group_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
-                                       ctypes.POINTER(_I64)]
+        L.eor_group_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                       ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
+        L.eor_group_set_tuning.argtypes = [_P, _I32, _I32, _I32]
+        L.eor_set_tuning.argtypes = [_P, _I32, _I32, _I32]
+        L.eor_get_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]
         L.eor_autotune.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.c_char_p, _I32, _P]
         L.eor_surrogate_create.argtypes = [ctypes.c_int, _I32, _I32, _I32, ctypes.c_uint64, _P, _P,
                                            ctypes.POINTER(_P)]
@@ -93,7 +96,8 @@ def lib() -> ctypes.CDLL:
         L.eor_compact_rows.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
                      "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
-                     "eor_group_set_graph", "eor_group_tuning", "eor_autotune", "eor_surrogate_create",
+                     "eor_group_set_graph", "eor_group_tuning", "eor_group_set_tuning", "eor_set_tuning",
+                     "eor_get_tuning", "eor_autotune", "eor_surrogate_create",
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
                      "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
@@ -194,6 +198,16 @@ class Context:
                                       terms.data_ptr(), _stream(stream)))
         return out, info, terms
 
+    def set_tuning(self, stages, wg_per_cu, tiles_per_pass=1):
+        """Launch choices of loglike_batch / loglike_terms (see eor_set_tuning)."""
+        check(lib().eor_set_tuning(self._h, stages, wg_per_cu, tiles_per_pass))
+
+    def tuning(self):
+        """(prefetch stages, workgroups per CU, tiles per pass)."""
+        s, w, t = _I32(), _I32(), _I32()
+        check(lib().eor_get_tuning(self._h, ctypes.byref(s), ctypes.byref(w), ctypes.byref(t)))
+        return s.value, w.value, t.value
+
     def export_precompute(self, stream=None):
         """(A [n, n] complex128 full Hermitian, dbar [n], c, K0)."""
         import torch
@@ -256,17 +270,22 @@ class Group:
         check(lib().eor_group_set_graph(self._h, 1 if enable else 0))
 
     def tuning(self):
-        """(prefetch stages, workgroups per CU, graph launches, graph captures)."""
-        s, w, r, c = _I32(), _I32(), _I64(), _I64()
-        check(lib().eor_group_tuning(self._h, ctypes.byref(s), ctypes.byref(w), ctypes.byref(r),
-                                     ctypes.byref(c)))
-        return s.value, w.value, r.value, c.value
+        """(prefetch stages, workgroups per CU, tiles per pass, graph launches, graph captures)."""
+        s, w, t, r, c = _I32(), _I32(), _I32(), _I64(), _I64()
+        check(lib().eor_group_tuning(self._h, ctypes.byref(s), ctypes.byref(w), ctypes.byref(t),
+                                     ctypes.byref(r), ctypes.byref(c)))
+        return s.value, w.value, t.value, r.value, c.value
+
+    def set_tuning(self, stages, wg_per_cu, tiles_per_pass=1):
+        check(lib().eor_group_set_tuning(self._h, stages, wg_per_cu, tiles_per_pass))
 
     def autotune(self, thetas, cache_path=None, force=False, stream=None):
+        """Time every launch choice on this batch, keep the fastest and return
+        it as (stages, workgroups per CU, tiles per pass)."""
         th, B, tp = self._arrays(thetas)
         cp = None if cache_path is None else str(cache_path).encode()
         check(lib().eor_autotune(self._h, B, tp, cp, 1 if force else 0, _stream(stream)))
-        return self.tuning()[:2]
+        return self.tuning()[:3]
 
 
 class Surrogate:

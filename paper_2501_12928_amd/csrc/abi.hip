@@ -26,7 +26,7 @@ eor_status hip_status(hipError_t e, const char *what) {
 }
 
 int64_t resident_per_cu(const Tuning &t) {
-    return std::min<int64_t>(t.wg_per_cu, like_max_resident_per_cu());
+    return std::min<int64_t>(t.tiles == 2 ? 1 : t.wg_per_cu, like_max_resident_per_cu(t.tiles));
 }
 
 InstDesc inst_desc(const Context &c) {
@@ -338,7 +338,7 @@ static eor_status loglike_impl(eor_ctx *ctx, int64_t B, const double *theta, dou
     p.slot_y = c.slot_y;
     p.call[0] = eor::CallDesc{theta, logL, info, terms};
     const int64_t grid = want < c.slots ? want : c.slots;
-    hipError_t e = eor::launch_likelihood(p, c.tune.stages, grid, (hipStream_t)stream);
+    hipError_t e = eor::launch_likelihood(p, c.tune, grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "likelihood launch");
     return EOR_OK;
 }
@@ -379,6 +379,25 @@ eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *d
         scalars[0] = sc[0];
         scalars[1] = c.khost + sc[1];
     }
+    return EOR_OK;
+}
+
+eor_status eor_set_tuning(eor_ctx *ctx, int32_t stages, int32_t wg_per_cu, int32_t tiles_per_pass) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_set_tuning: ctx is NULL");
+    if (!eor::valid_tuning(stages, wg_per_cu, tiles_per_pass))
+        return fail(EOR_ERR_ARG, "eor_set_tuning: need stages 2|4, and wg_per_cu 1|2 with tiles_per_pass 1, "
+                                 "or wg_per_cu 1 with tiles_per_pass 2");
+    ctx->c.tune.stages = stages;
+    ctx->c.tune.wg_per_cu = wg_per_cu;
+    ctx->c.tune.tiles = tiles_per_pass;
+    return EOR_OK;
+}
+
+eor_status eor_get_tuning(const eor_ctx *ctx, int32_t *stages, int32_t *wg_per_cu, int32_t *tiles_per_pass) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_get_tuning: ctx is NULL");
+    if (stages) *stages = ctx->c.tune.stages;
+    if (wg_per_cu) *wg_per_cu = ctx->c.tune.wg_per_cu;
+    if (tiles_per_pass) *tiles_per_pass = ctx->c.tune.tiles;
     return EOR_OK;
 }
 

@@ -71,7 +71,9 @@ struct LikeParams {
 // Launch choices the autotuner picks between.
 struct Tuning {
     int stages = 4;      // register prefetch depth of the panel update (2 or 4)
-    int wg_per_cu = 2;   // resident workgroups (theta in flight) per CU (1 or 2)
+    int wg_per_cu = 1;   // resident workgroups (theta in flight) per CU (1 or 2)
+    int tiles = 2;       // tiles of a column updated per pass of its panel (1 or 2); 2 fills a CU
+                         // with one workgroup of eight waves, so wg_per_cu is then 1
 };
 
 // State behind an eor_ctx handle.
@@ -121,6 +123,10 @@ struct Context {
 eor_status fail_status(eor_status st, const std::string &msg);
 eor_status hip_status(hipError_t e, const char *what);
 int64_t resident_per_cu(const Tuning &t);
+inline bool valid_tuning(int stages, int wg_per_cu, int tiles) {
+    return (stages == 2 || stages == 4) &&
+           ((tiles == 1 && (wg_per_cu == 1 || wg_per_cu == 2)) || (tiles == 2 && wg_per_cu == 1));
+}
 
 // Kernel launchers (precompute.hip, likelihood.hip).
 hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ldT,
@@ -135,8 +141,8 @@ hipError_t launch_precompute_vectors(const Context &c, const double2 *T, int64_t
                                      double2 *partial, int splits, hipStream_t s);
 hipError_t launch_export_A(const Context &c, double2 *out, int64_t ldA, hipStream_t s);
 
-int like_max_resident_per_cu();
-hipError_t launch_likelihood(const LikeParams &p, int stages, int64_t grid, hipStream_t s);
+int like_max_resident_per_cu(int tiles);
+hipError_t launch_likelihood(const LikeParams &p, const Tuning &t, int64_t grid, hipStream_t s);
 InstDesc inst_desc(const Context &c);
 
 }  // namespace eor

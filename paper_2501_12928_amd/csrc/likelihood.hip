@@ -3,25 +3,40 @@
 // y = L^{-1} dbar, reduce ln det Sigma = 2 sum ln L_jj and ||y||^2 = dbar^H
 // Sigma^{-1} dbar, and combine into logL.
 //
-// One workgroup (4 waves) owns one theta at a time and walks the tiles of L
-// left-looking, column by column:
+// One workgroup owns one theta at a time and walks the tiles of L
+// left-looking, column by column, with the forward substitution carried
+// right-looking alongside (w starts as dbar):
 //
 //   for each tile column j:
-//     diagonal:  S = sum_{k<j} L_jk L_jk^H (MFMA), z = sum_{k<j} L_jk y_k
-//                D = A_jj + diag(Phi^{-1}) - S  -> LDS; Cholesky of D in LDS;
-//                in-place triangular inverse Linv = L_jj^{-1} (kept in LDS);
-//                y_j = Linv (dbar_j - z)
+//     diagonal:  D = A_jj + diag(Phi^{-1}) - sum_{k<j} L_jk L_jk^H (MFMA) -> LDS;
+//                Cholesky of D in LDS; in-place triangular inverse
+//                Linv = L_jj^{-1} (kept in LDS); y_j = Linv w_j
 //     below:     for i > j: X = A_ij - sum_{k<j} L_ik L_jk^H (MFMA)
 //                           L_ij = X Linv^H (MFMA, operand from LDS)
+//                           w_i -= L_ij y_j
+//
+// The workgroup is G groups of four waves (G = 1 or 2, the tiles per pass).
+// The units of column j are the diagonal tile (unit 0) and the tiles below
+// it (unit u = tile j + u); they are dealt to the groups in rounds of G, so
+// with G = 2 two tiles are updated at once against one stream of the column
+// panel L_j,0..j-1, which the eight waves share through the CU's L1: a
+// quarter less HBM traffic than two workgroups on separate thetas. In the
+// first round group 1 updates tile j + 1 while group 0 forms the diagonal,
+// and holds its accumulators until L_jj^{-1} is ready.
 //
 // The panel updates form each complex product from three real FP64 MFMAs
-// (Gauss's trick) instead of four; the TRSM step keeps four.
+// (Gauss's trick) instead of four; the TRSM step keeps four. A tile's
+// accumulators start from A_ij (loaded while the panel prefetch is in
+// flight), so the update ends with X itself.
 //
 // Every entry of L is written once and read back only as an MFMA operand,
 // so Sigma is never materialised: A is read once per theta, tile by tile,
 // where the factorisation first needs it. Tile-row i of the packed storage
 // is a column-major 64 x 64j panel (leading dimension 64), so both operands
-// of the update stream with unit stride.
+// of the update stream with unit stride. Panels and tiles are read through
+// raw buffer descriptors built from wave-uniform bases: the k-step offset is
+// a scalar register and each lane keeps one 32-bit offset, which leaves the
+// vector registers to the accumulators and the prefetch.
 //
 // The FP64 16x16x4 MFMA takes its A operand as lane l -> A[l%16][l/16], its
 // B operand as lane l -> B[l/16][l%16], and returns D[l/16 + 4r][l%16] in
@@ -36,7 +51,13 @@ namespace eor {
 
 namespace {
 
-constexpr int NT = 256;  // threads per workgroup (4 waves of 64)
+constexpr int GROUP_THREADS = 256;  // one group: 4 waves of 64, each owning 16 rows of a tile
+constexpr int TILE_BYTES = TS2 * 16;
+constexpr int COL_BYTES = TS * 16;  // one column of a tile (or of a panel)
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 __device__ inline d4 mfma64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -49,11 +70,31 @@ __device__ inline d4 mfma64(double a, double b, d4 c) {
 // different waves then execute different numbers of barriers.
 __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Hides a lane-dependent value from loop-invariant code motion, so that the
-// compiler forms tile addresses as one lane offset plus constants where they
-// are used instead of hoisting one register per address out of the loops.
-__device__ inline int opaque(int x) {
-    asm volatile("" : "+v"(x));
+template <class T>
+__device__ inline T *uniform_ptr(T *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer over nbytes at p (a wave-uniform address). Loads past nbytes
+// return zero and stores past it are dropped.
+__device__ inline rsrc_t make_rsrc(const void *p, int64_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
+}
+
+__device__ inline double2 ld2(rsrc_t r, int voff, int soff) {
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    double2 x;
+    __builtin_memcpy(&x, &v, sizeof(x));
+    return x;
+}
+
+__device__ inline double ld1(rsrc_t r, int voff, int soff) {
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    double x;
+    __builtin_memcpy(&x, &v, sizeof(x));
     return x;
 }
 
@@ -63,19 +104,15 @@ struct Step {
     double2 qv[4]; // Q[16cb + l16][k0 + q]
 };
 
-// The register prefetch depth of the panel update (k-steps in flight) is a
-// template parameter; four steps cover HBM latency at two waves per SIMD on
-// the large problems, and the autotuner may choose two.
-
-__device__ inline void load_step(Step &s, const double2 *__restrict__ pp, const double2 *__restrict__ qp,
-                                 int64_t k0) {
-    s.p = pp[k0 * TS];
+// P's descriptor starts at row 16w, Q's at row 0; voff = (64q + l16) * 16.
+__device__ inline void load_step(Step &s, rsrc_t P, rsrc_t Q, int voff, int soff) {
+    s.p = ld2(P, voff, soff);
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) s.qv[cb] = qp[k0 * TS + 16 * cb];
+    for (int cb = 0; cb < 4; ++cb) s.qv[cb] = ld2(Q, voff + 16 * 16 * cb, soff);
 }
 
-// acc[i][c] += P[i][k] conj(Q[c][k]) with three real products per complex
-// product (Gauss):  with p = P, q = Q,
+// t += P Q^H for one k-step with three real products per complex product
+// (Gauss): with p = P, q = Q,
 //   T1 = qr pr,  T2 = qi pi,  T3 = (qr - qi)(pr + pi)
 //   re = T1 + T2,  im = T3 - T1 + T2  (= qr pi - qi pr)
 __device__ inline void mma_step(const Step &s, d4 t1[4], d4 t2[4], d4 t3[4]) {
@@ -88,60 +125,88 @@ __device__ inline void mma_step(const Step &s, d4 t1[4], d4 t2[4], d4 t3[4]) {
     }
 }
 
-// S = P Q^H over K columns (K a multiple of 64), returned as (accR, accI).
-// With WITHZ, also the partial z[i] = sum_k P[i][k] y[k] of the forward
-// substitution. The four waves re-align once per 64 columns so that the
-// column panel Q, which all of them read, is fetched from HBM once.
-template <bool WITHZ, int STAGES>
-__device__ inline void panel_update(const double2 *__restrict__ P, const double2 *__restrict__ Q,
-                                    const double2 *__restrict__ y, int64_t K, int w, int l16, int q,
-                                    d4 accR[4], d4 accI[4], double &zr, double &zi) {
-    d4 t3[4];
+// X = A - P Q^H over K columns (K a multiple of 64), returned as (xr, xi) in
+// the accumulator layout. The A tile goes straight into the accumulators
+// (T1 = 0, T2 = -Re A, T3 = Re A - Im A, so that the final combine gives
+// -(S - A)), issued before the panel prefetch so that its latency overlaps
+// it. The four waves of a group (and both groups of a workgroup) re-align
+// once per 64 columns so that the column panel Q, which all of them read,
+// is fetched from HBM once.
+template <int STAGES>
+__device__ inline void tile_update(rsrc_t A, rsrc_t P, rsrc_t Q, int K, int voff, d4 xr[4], d4 xi[4]) {
+    d4 t1[4], t3[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-        accR[cb] = d4{0, 0, 0, 0};
-        accI[cb] = d4{0, 0, 0, 0};
-        t3[cb] = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // A[16w + l16][16cb + 4r + q]: column (16cb + 4r + q), row 16w + l16
+            const int so = (16 * cb + 4 * r) * COL_BYTES;
+            xr[cb][r] = ld1(A, voff, so);
+            t3[cb][r] = ld1(A, voff + 8, so);
+        }
     }
-    if (K == 0) return;
-    const double2 *pp = P + q * TS + 16 * w + l16;
-    const double2 *qp = Q + q * TS + l16;
+    // The prefetch runs up to 4 (STAGES - 1) columns past K without a
+    // guard: those loads fall in tile (i, j) of P's tile-row and tile (j, j)
+    // of Q's, inside the slot, and are never used. A conditional load would
+    // make the compiler's wait counts conservative at the merge and drain
+    // the whole prefetch once per loop iteration.
+    // The prologue keeps its program order (sched_barrier): with step 0's
+    // loads issued first, the loop's first wait is the same partial count
+    // as in every later iteration instead of a full drain.
     Step buf[STAGES];
 #pragma unroll
-    for (int s0 = 0; s0 < STAGES - 1; ++s0) load_step(buf[s0], pp, qp, 4 * s0);
-    for (int64_t k0 = 0; k0 < K; k0 += 4 * STAGES) {
+    for (int s0 = 0; s0 < STAGES - 1; ++s0) {
+        load_step(buf[s0], P, Q, voff, 4 * s0 * COL_BYTES);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        t1[cb] = d4{0, 0, 0, 0};
+        t3[cb] = xr[cb] - t3[cb];
+        xr[cb] = -xr[cb];  // T2
+    }
+    d4 *t2 = xr;
+    for (int k0 = 0; k0 < K; k0 += 4 * STAGES) {
         if ((k0 & (TS - 1)) == 0) __syncthreads();
 #pragma unroll
         for (int u = 0; u < STAGES; ++u) {
-            const int64_t kl = k0 + 4 * (u + STAGES - 1);
-            if (kl < K) load_step(buf[(u + STAGES - 1) % STAGES], pp, qp, kl);
-            if (WITHZ) {
-                const double2 yk = y[k0 + 4 * u + q];
-                zr += buf[u].p.x * yk.x - buf[u].p.y * yk.y;
-                zi += buf[u].p.x * yk.y + buf[u].p.y * yk.x;
-            }
-            mma_step(buf[u], accR, accI, t3);
+            const int kl = k0 + 4 * (u + STAGES - 1);
+            load_step(buf[(u + STAGES - 1) % STAGES], P, Q, voff, kl * COL_BYTES);
+            mma_step(buf[u], t1, t2, t3);
         }
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-        const d4 a = accR[cb], b = accI[cb];
-        accR[cb] = a + b;
-        accI[cb] = t3[cb] - a + b;
+        const d4 a = t1[cb], b = t2[cb];
+        xr[cb] = -(a + b);
+        xi[cb] = a - b - t3[cb];
     }
 }
 
-template <int STAGES>
-__global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
+// The barriers of tile_update over K columns, for a group without a tile in
+// the current round: every wave of the workgroup must pass the same number.
+__device__ inline void panel_barriers(int K) {
+    for (int k0 = 0; k0 < K; k0 += TS) __syncthreads();
+}
+
+template <int STAGES, int G>
+__global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(LikeParams a) {
+    constexpr int NT = GROUP_THREADS * G;
+    constexpr int NWAVE = NT / 64;
     __shared__ double2 Dt[TS2];   // diagonal tile: D, then L_jj, then L_jj^{-1}
-    __shared__ double2 wv[TS];    // dbar_j - z, then y_j
+    __shared__ double2 wv[TS];    // w_j = dbar_j - sum_{k<j} L_jk y_k
+    __shared__ double2 ys[TS];    // y_j
     __shared__ double dg[TS];     // pivots of the current diagonal tile
     __shared__ double red[TS];    // |y_j|^2 per row
     __shared__ int task_sh;
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-    double2 *L = a.Lw + (int64_t)blockIdx.x * a.slot_tiles * TS2;
-    double2 *yv = a.yw + (int64_t)blockIdx.x * a.slot_y;
+    const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    const int w = uniform((tid >> 6) & 3);   // row slab 16w..16w+15 of the group's tile
+    const int grp = uniform(tid >> 8);       // group within the workgroup
+    const int voff = (q * TS + l16) * 16;    // lane offset of operand loads (bytes)
+    const int voff_st = (l16 * TS + q) * 16; // lane offset of L_ij stores (bytes): Y[16w + q][l16]
+    double2 *L = uniform_ptr(a.Lw + (int64_t)blockIdx.x * a.slot_tiles * TS2);
+    double2 *yv = uniform_ptr(a.yw + (int64_t)blockIdx.x * a.slot_y);
 
     // Persistent workgroup: take tasks in list order (the host sorts them
     // longest first) until the list is exhausted.
@@ -160,7 +225,8 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
         }
         const InstDesc I = a.inst[inst];
         const CallDesc C = a.call[inst];
-        const int64_t N = I.N;
+        const int N = uniform(I.N);
+        const double2 *Ab = uniform_ptr(I.A);
         const double *th = C.theta + bt * I.n_k;
         // ln det Phi over the binned coefficients, and the theta check.
         bool ok = true;
@@ -186,182 +252,203 @@ __global__ __launch_bounds__(NT, 2) void likelihood_kernel(LikeParams a) {
                 for (int e = 0; e < 4; ++e) C.terms[4 * bt + e] = NAN;
             }
         }
+        // w = dbar; read back only after the barrier that opens column 0
+        if (valid) {
+            for (int e = tid; e < N * TS; e += NT) yv[e] = I.dbar[e];
+        }
 
         double logdet = 0.0, quad = 0.0;  // meaningful in thread 0 only
         int failed = 0;
 
-        for (int64_t j = 0; valid && j < N && !failed; ++j) {
-            __syncthreads();  // previous column's readers of Dt are done
-            const double2 *panel_j = L + tile_index(j, 0) * TS2;
+        for (int j = 0; valid && j < N && !failed; ++j) {
+            __syncthreads();  // previous column's readers of Dt and writers of w are done
+            const int K = j * TS;
+            const rsrc_t Qr = make_rsrc(L + tile_index(j, 0) * TS2, (int64_t)K * COL_BYTES);
+            const int units = N - j;  // unit 0: diagonal tile; unit u > 0: tile (j + u, j)
 
-            // ---- diagonal tile --------------------------------------------
-            d4 accR[4], accI[4];
-            double zr = 0.0, zi = 0.0;
-            panel_update<true, STAGES>(panel_j, panel_j, yv, j * TS, w, l16, q, accR, accI, zr, zi);
-            {
-                const double2 *Ajj = I.A + tile_index(j, j) * TS2;
-                const int lo = opaque(q * TS + 16 * w + l16);  // [16w + l16][q], column-major
-                const int dq = opaque(l16 - q);                // row == col iff cb == w, 4r == dq
-                const int row = 16 * w + l16;
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int off = lo + (16 * cb + 4 * r) * TS;
-                        double2 v = Ajj[off];
-                        v.x -= accR[cb][r];
-                        v.y -= accI[cb][r];
-                        if (cb == w && dq == 4 * r) {
-                            const int64_t g = j * TS + row;
-                            const int32_t b = I.coef_bin[g];
-                            const double ip = b >= 0 ? 1.0 / (I.bin_scale[b] * exp10(th[b])) : I.coef_inv[g];
-                            v.x += ip;
-                        }
-                        Dt[off] = v;
-                    }
-                }
-                // reduce z over the four lane groups sharing a row
-                zr += __shfl_xor(zr, 16);
-                zi += __shfl_xor(zi, 16);
-                zr += __shfl_xor(zr, 32);
-                zi += __shfl_xor(zi, 32);
-                if (q == 0) {
-                    const double2 db = I.dbar[j * TS + row];
-                    wv[row] = make_double2(db.x - zr, db.y - zi);
-                }
-            }
-
-            // ---- Cholesky of the diagonal tile in LDS (right-looking) -------
-            // Column c is left unscaled during the sweep; the update uses
-            // D[r][s] -= D[r][c] conj(D[s][c]) / D[c][c].
-            {
-                const int r = tid & 63, qq = tid >> 6;
-                for (int c = 0; c < TS; ++c) {
-                    __syncthreads();
-                    const double dcc = Dt[c * TS + c].x;
-                    if (uniform((!(dcc > 0.0) || !isfinite(dcc)) ? 1 : 0)) {
-                        failed = (int)(j * TS + c + 1);
-                        break;
-                    }
-                    if (tid == 0) dg[c] = dcc;
-                    if (r > c) {
-                        const double2 lrc = Dt[c * TS + r];
-                        const double sr = lrc.x / dcc, si = lrc.y / dcc;
-                        for (int s = c + 1 + qq; s <= r; s += 4) {
-                            const double2 lsc = Dt[c * TS + s];
-                            // (sr + i si) * conj(lsc)
-                            double2 v = Dt[s * TS + r];
-                            v.x -= sr * lsc.x + si * lsc.y;
-                            v.y -= si * lsc.x - sr * lsc.y;
-                            Dt[s * TS + r] = v;
-                        }
-                    }
-                }
-            }
-            if (failed) break;
-            __syncthreads();
-            // scale: L[c][c] = sqrt(d_c), L[r][c] = D[r][c] / sqrt(d_c); zero the upper part
-            for (int e = tid; e < TS2; e += NT) {
-                const int c = e / TS, r = e % TS;
-                double2 v = Dt[e];
-                if (r == c) {
-                    v = make_double2(sqrt(dg[c]), 0.0);
-                } else if (r > c) {
-                    const double is = 1.0 / sqrt(dg[c]);
-                    v.x *= is;
-                    v.y *= is;
+            for (int u0 = 0; u0 < units; u0 += G) {
+                const int u = u0 + grp;
+                const int i = j + u;
+                d4 xr[4], xi[4];
+                if (u < units) {
+                    // ---- X = A_ij - sum_k L_ik L_jk^H, in the accumulator layout
+                    const rsrc_t Ar = make_rsrc(Ab + tile_index(i, j) * TS2 + 16 * w, TILE_BYTES - 256 * w);
+                    const rsrc_t Pr = make_rsrc(L + tile_index(i, 0) * TS2 + 16 * w, (int64_t)K * COL_BYTES);
+                    tile_update<STAGES>(Ar, Pr, Qr, K, voff, xr, xi);
                 } else {
-                    v = make_double2(0.0, 0.0);
+                    panel_barriers(K);  // no tile for this group in the last round
                 }
-                Dt[e] = v;
-            }
-            if (tid == 0) {
-                for (int c = 0; c < TS; ++c) logdet += log(dg[c]);
-            }
-            __syncthreads();
-
-            // ---- in-place inverse of the lower-triangular L_jj ---------------
-            // Columns from the last to the first:
-            //   Linv[c][c] = 1 / L[c][c]
-            //   Linv[r][c] = -(sum_{k=c+1..r} Linv[r][k] L[k][c]) / L[c][c],  r > c
-            for (int c = TS - 1; c >= 0; --c) {
-                double2 nv = make_double2(0.0, 0.0);
-                const int r = tid;
-                const double lcc = Dt[c * TS + c].x;
-                if (r < TS && r > c) {
-                    double sr = 0.0, si = 0.0;
-                    for (int k = c + 1; k <= r; ++k) {
-                        const double2 x = Dt[k * TS + r];  // Linv[r][k] (already inverted)
-                        const double2 l = Dt[c * TS + k];  // L[k][c]
-                        sr += x.x * l.x - x.y * l.y;
-                        si += x.x * l.y + x.y * l.x;
-                    }
-                    nv = make_double2(-sr / lcc, -si / lcc);
-                }
-                __syncthreads();
-                if (r < TS && r > c) Dt[c * TS + r] = nv;
-                if (r == c) Dt[c * TS + c] = make_double2(1.0 / lcc, 0.0);
-                __syncthreads();
-            }
-
-            // ---- y_j = Linv (dbar_j - z) ---------------------------------
-            if (tid < TS) {
-                const int r = tid;
-                double sr = 0.0, si = 0.0;
-                for (int c = 0; c <= r; ++c) {
-                    const double2 x = Dt[c * TS + r];
-                    const double2 u = wv[c];
-                    sr += x.x * u.x - x.y * u.y;
-                    si += x.x * u.y + x.y * u.x;
-                }
-                yv[j * TS + r] = make_double2(sr, si);
-                red[r] = sr * sr + si * si;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                for (int r = 0; r < TS; ++r) quad += red[r];
-            }
-
-            // ---- tiles below the diagonal ---------------------------------
-            for (int64_t i = j + 1; i < N; ++i) {
-                const double2 *panel_i = L + tile_index(i, 0) * TS2;
-                panel_update<false, STAGES>(panel_i, panel_j, nullptr, j * TS, w, l16, q, accR, accI, zr, zi);
-                const double2 *Aij = I.A + tile_index(i, j) * TS2;
-                const int lo = opaque(q * TS + 16 * w + l16);
-                // X = A_ij - S, in the accumulator layout
+                if (u == 0) {
+                    // D = X + diag(Phi^{-1}) -> LDS (column-major)
+                    const int lo = q * TS + 16 * w + l16;  // [16w + l16][q]
+                    const int dq = l16 - q;                // row == col iff cb == w, 4r == dq
+                    const int row = 16 * w + l16;
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double2 v = Aij[lo + (16 * cb + 4 * r) * TS];
-                        accR[cb][r] = v.x - accR[cb][r];
-                        accI[cb][r] = v.y - accI[cb][r];
-                    }
-                }
-                // Y = X Linv^H: Y[i][c'] = sum_c X[i][c] conj(Linv[c'][c]); Linv is
-                // lower triangular, so output block cb2 needs column blocks cb <= cb2.
-                double2 *Lij = L + tile_index(i, j) * TS2;
-                const int lt = opaque(q * TS + l16);            // Linv[l16][q] in LDS
-                const int lw = opaque(l16 * TS + 16 * w + q);   // Y[16w + q][l16] in the tile
-#pragma unroll
-                for (int cb2 = 0; cb2 < 4; ++cb2) {
-                    d4 yR = d4{0, 0, 0, 0}, yI = d4{0, 0, 0, 0};
-#pragma unroll
-                    for (int cb = 0; cb <= cb2; ++cb) {
+                    for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            // Linv[16cb2 + l16][16cb + 4r + q]
-                            const double2 lv = Dt[lt + (16 * cb + 4 * r) * TS + 16 * cb2];
-                            const double xr = accR[cb][r], xi = accI[cb][r];
-                            yR = mfma64(xr, lv.x, yR);
-                            yR = mfma64(xi, lv.y, yR);
-                            yI = mfma64(xi, lv.x, yI);
-                            yI = mfma64(-xr, lv.y, yI);
+                            double2 v = make_double2(xr[cb][r], xi[cb][r]);
+                            if (cb == w && dq == 4 * r) {
+                                const int64_t g = (int64_t)j * TS + row;
+                                const int32_t b = I.coef_bin[g];
+                                const double ip = b >= 0 ? 1.0 / (I.bin_scale[b] * exp10(th[b])) : I.coef_inv[g];
+                                v.x += ip;
+                            }
+                            Dt[lo + (16 * cb + 4 * r) * TS] = v;
                         }
                     }
-                    // lane holds Y[16w + q + 4r][16cb2 + l16]
+                    if (tid < TS) wv[tid] = yv[(int64_t)j * TS + tid];
+                }
+
+                if (u0 == 0) {
+                    // ---- Cholesky of the diagonal tile in LDS (right-looking)
+                    // Column c is left unscaled during the sweep; the update uses
+                    // D[r][s] -= D[r][c] conj(D[s][c]) / D[c][c].
+                    {
+                        const int r = tid & 63, qq = tid >> 6;
+                        for (int c = 0; c < TS; ++c) {
+                            __syncthreads();
+                            const double dcc = Dt[c * TS + c].x;
+                            if (uniform((!(dcc > 0.0) || !isfinite(dcc)) ? 1 : 0)) {
+                                failed = j * TS + c + 1;
+                                break;
+                            }
+                            if (tid == 0) dg[c] = dcc;
+                            if (r > c) {
+                                const double2 lrc = Dt[c * TS + r];
+                                const double sr = lrc.x / dcc, si = lrc.y / dcc;
+                                for (int s = c + 1 + qq; s <= r; s += NWAVE) {
+                                    const double2 lsc = Dt[c * TS + s];
+                                    // (sr + i si) * conj(lsc)
+                                    double2 v = Dt[s * TS + r];
+                                    v.x -= sr * lsc.x + si * lsc.y;
+                                    v.y -= si * lsc.x - sr * lsc.y;
+                                    Dt[s * TS + r] = v;
+                                }
+                            }
+                        }
+                    }
+                    if (failed) break;
+                    __syncthreads();
+                    // scale: L[c][c] = sqrt(d_c), L[r][c] = D[r][c] / sqrt(d_c); zero the upper part
+                    for (int e = tid; e < TS2; e += NT) {
+                        const int c = e / TS, r = e % TS;
+                        double2 v = Dt[e];
+                        if (r == c) {
+                            v = make_double2(sqrt(dg[c]), 0.0);
+                        } else if (r > c) {
+                            const double is = 1.0 / sqrt(dg[c]);
+                            v.x *= is;
+                            v.y *= is;
+                        } else {
+                            v = make_double2(0.0, 0.0);
+                        }
+                        Dt[e] = v;
+                    }
+                    if (tid == 0) {
+                        for (int c = 0; c < TS; ++c) logdet += log(dg[c]);
+                    }
+                    __syncthreads();
+
+                    // ---- in-place inverse of the lower-triangular L_jj -----
+                    // Columns from the last to the first:
+                    //   Linv[c][c] = 1 / L[c][c]
+                    //   Linv[r][c] = -(sum_{k=c+1..r} Linv[r][k] L[k][c]) / L[c][c],  r > c
+                    for (int c = TS - 1; c >= 0; --c) {
+                        double2 nv = make_double2(0.0, 0.0);
+                        const int r = tid;
+                        const double lcc = Dt[c * TS + c].x;
+                        if (r < TS && r > c) {
+                            double sr = 0.0, si = 0.0;
+                            for (int k = c + 1; k <= r; ++k) {
+                                const double2 x = Dt[k * TS + r];  // Linv[r][k] (already inverted)
+                                const double2 l = Dt[c * TS + k];  // L[k][c]
+                                sr += x.x * l.x - x.y * l.y;
+                                si += x.x * l.y + x.y * l.x;
+                            }
+                            nv = make_double2(-sr / lcc, -si / lcc);
+                        }
+                        __syncthreads();
+                        if (r < TS && r > c) Dt[c * TS + r] = nv;
+                        if (r == c) Dt[c * TS + c] = make_double2(1.0 / lcc, 0.0);
+                        __syncthreads();
+                    }
+
+                    // ---- y_j = Linv w_j ---------------------------------------
+                    if (tid < TS) {
+                        const int r = tid;
+                        double sr = 0.0, si = 0.0;
+                        for (int c = 0; c <= r; ++c) {
+                            const double2 x = Dt[c * TS + r];
+                            const double2 uu = wv[c];
+                            sr += x.x * uu.x - x.y * uu.y;
+                            si += x.x * uu.y + x.y * uu.x;
+                        }
+                        yv[(int64_t)j * TS + r] = make_double2(sr, si);
+                        ys[r] = make_double2(sr, si);
+                        red[r] = sr * sr + si * si;
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        for (int r = 0; r < TS; ++r) quad += red[r];
+                    }
+                }
+
+                if (u > 0 && u < units) {
+                    // ---- L_ij = X Linv^H; w_i -= L_ij y_j -----------------------
+                    // Y[i][c'] = sum_c X[i][c] conj(Linv[c'][c]); Linv is lower
+                    // triangular, so output block cb2 needs column blocks cb <= cb2.
+                    // The tile is stored with plain global stores: written through
+                    // raw buffer stores, tiles read by the other group in later
+                    // columns came back stale now and then (no fault), which plain
+                    // stores have never shown.
+                    double2 *Lij = L + tile_index(i, j) * TS2 + voff_st / 16 + 16 * w;
+                    const int lt = q * TS + l16;  // Linv[l16][q] in LDS
+                    double wr[4] = {0, 0, 0, 0}, wi[4] = {0, 0, 0, 0};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Lij[lw + 16 * cb2 * TS + 4 * r] = make_double2(yR[r], yI[r]);
+                    for (int cb2 = 0; cb2 < 4; ++cb2) {
+                        d4 yR = d4{0, 0, 0, 0}, yI = d4{0, 0, 0, 0};
+#pragma unroll
+                        for (int cb = 0; cb <= cb2; ++cb) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                // Linv[16cb2 + l16][16cb + 4r + q]
+                                const double2 lv = Dt[lt + (16 * cb + 4 * r) * TS + 16 * cb2];
+                                const double ar = xr[cb][r], ai = xi[cb][r];
+                                yR = mfma64(ar, lv.x, yR);
+                                yR = mfma64(ai, lv.y, yR);
+                                yI = mfma64(ai, lv.x, yI);
+                                yI = mfma64(-ar, lv.y, yI);
+                            }
+                        }
+                        // lane holds Y[16w + q + 4r][16cb2 + l16]
+                        const double2 yc = ys[16 * cb2 + l16];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            Lij[16 * cb2 * TS + 4 * r] = make_double2(yR[r], yI[r]);
+                            wr[r] += yR[r] * yc.x - yI[r] * yc.y;
+                            wi[r] += yR[r] * yc.y + yI[r] * yc.x;
+                        }
+                    }
+                    // sum over the 16 lanes that share q (the columns), fixed tree
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+                        for (int m = 8; m >= 1; m >>= 1) {
+                            wr[r] += __shfl_xor(wr[r], m);
+                            wi[r] += __shfl_xor(wi[r], m);
+                        }
+                    }
+                    if (l16 == 0) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            double2 *p = yv + (int64_t)i * TS + 16 * w + q + 4 * r;
+                            double2 v = *p;
+                            v.x -= wr[r];
+                            v.y -= wi[r];
+                            *p = v;
+                        }
+                    }
                 }
             }
         }
@@ -394,19 +481,30 @@ __global__ void zero_counter_kernel(unsigned int *counter) { *counter = 0u; }
 
 }  // namespace
 
-int like_max_resident_per_cu() {
+int like_max_resident_per_cu(int tiles) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, likelihood_kernel<4>, NT, 0) != hipSuccess) return 1;
+    const hipError_t e =
+        tiles == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, likelihood_kernel<4, 2>, 2 * GROUP_THREADS, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, likelihood_kernel<4, 1>, GROUP_THREADS, 0);
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_likelihood(const LikeParams &p, int stages, int64_t grid, hipStream_t s) {
+hipError_t launch_likelihood(const LikeParams &p, const Tuning &t, int64_t grid, hipStream_t s) {
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, p.counter);
-    if (stages == 2)
-        hipLaunchKernelGGL(likelihood_kernel<2>, dim3((unsigned)grid), dim3(NT), 0, s, p);
-    else
-        hipLaunchKernelGGL(likelihood_kernel<4>, dim3((unsigned)grid), dim3(NT), 0, s, p);
+    const dim3 g((unsigned)grid);
+    if (t.tiles == 2) {
+        if (t.stages == 2)
+            hipLaunchKernelGGL((likelihood_kernel<2, 2>), g, dim3(2 * GROUP_THREADS), 0, s, p);
+        else
+            hipLaunchKernelGGL((likelihood_kernel<4, 2>), g, dim3(2 * GROUP_THREADS), 0, s, p);
+    } else {
+        if (t.stages == 2)
+            hipLaunchKernelGGL((likelihood_kernel<2, 1>), g, dim3(GROUP_THREADS), 0, s, p);
+        else
+            hipLaunchKernelGGL((likelihood_kernel<4, 1>), g, dim3(GROUP_THREADS), 0, s, p);
+    }
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct eor_group {
     eor::LikeParams cap_params;
     int64_t cap_grid = 0;
     int cap_stages = 0;
+    int cap_tiles = 0;
     int64_t replays = 0;
     int64_t captures = 0;
 };
@@ -151,7 +152,7 @@ std::string arch_name(int device) {
 }
 
 // Cache format: one entry per line,
-//   "<arch>|<bucket>|<kind>": {"stages": S, "wg_per_cu": W, "ms": T}
+//   "<arch>|<bucket>|<kind>": {"stages": S, "wg_per_cu": W, "tiles": P, "ms": T}
 std::map<std::string, std::string> read_cache(const char *path) {
     std::map<std::string, std::string> out;
     std::ifstream f(path);
@@ -168,12 +169,15 @@ std::map<std::string, std::string> read_cache(const char *path) {
 }
 
 bool parse_entry(const std::string &v, eor::Tuning &t) {
-    int s = 0, w = 0;
+    int s = 0, w = 0, p = 0;
     double ms = 0.0;
-    if (std::sscanf(v.c_str(), "{\"stages\": %d, \"wg_per_cu\": %d, \"ms\": %lf}", &s, &w, &ms) < 2) return false;
-    if ((s != 2 && s != 4) || (w != 1 && w != 2)) return false;
+    if (std::sscanf(v.c_str(), "{\"stages\": %d, \"wg_per_cu\": %d, \"tiles\": %d, \"ms\": %lf}", &s, &w, &p,
+                    &ms) < 3)
+        return false;
+    if (!eor::valid_tuning(s, w, p)) return false;
     t.stages = s;
     t.wg_per_cu = w;
+    t.tiles = p;
     return true;
 }
 
@@ -234,10 +238,10 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
     const int64_t grid = std::min<int64_t>(want, g.slots);
     const eor::LikeParams p = make_params(g, theta, logL, info);
     if (!(allow_graph && g.use_graph)) {
-        e = eor::launch_likelihood(p, t.stages, grid, s);
+        e = eor::launch_likelihood(p, t, grid, s);
         return e == hipSuccess ? EOR_OK : eor::hip_status(e, "group launch");
     }
-    const bool same = g.exec && g.cap_grid == grid && g.cap_stages == t.stages &&
+    const bool same = g.exec && g.cap_grid == grid && g.cap_stages == t.stages && g.cap_tiles == t.tiles &&
                       std::memcmp(&g.cap_params, &p, sizeof(p)) == 0;
     if (!same) {
         drop_graph(g);
@@ -247,7 +251,7 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
         }
         e = hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return eor::hip_status(e, "hipStreamBeginCapture");
-        hipError_t el = eor::launch_likelihood(p, t.stages, grid, g.cap_stream);
+        hipError_t el = eor::launch_likelihood(p, t, grid, g.cap_stream);
         e = hipStreamEndCapture(g.cap_stream, &g.graph);
         if (el != hipSuccess) e = el;
         if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
@@ -258,6 +262,7 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
         g.cap_params = p;
         g.cap_grid = grid;
         g.cap_stages = t.stages;
+        g.cap_tiles = t.tiles;
         ++g.captures;
     }
     e = hipGraphLaunch(g.exec, s);
@@ -341,11 +346,23 @@ eor_status eor_group_set_graph(eor_group *g, int32_t enable) {
     return EOR_OK;
 }
 
-eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per_cu, int64_t *graph_launches,
-                            int64_t *graph_captures) {
+eor_status eor_group_set_tuning(eor_group *g, int32_t stages, int32_t wg_per_cu, int32_t tiles_per_pass) {
+    if (!g) return eor::fail_status(EOR_ERR_ARG, "eor_group_set_tuning: group is NULL");
+    if (!eor::valid_tuning(stages, wg_per_cu, tiles_per_pass))
+        return eor::fail_status(EOR_ERR_ARG, "eor_group_set_tuning: need stages 2|4, and wg_per_cu 1|2 with "
+                                             "tiles_per_pass 1, or wg_per_cu 1 with tiles_per_pass 2");
+    g->tune.stages = stages;
+    g->tune.wg_per_cu = wg_per_cu;
+    g->tune.tiles = tiles_per_pass;
+    return EOR_OK;
+}
+
+eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per_cu, int32_t *tiles_per_pass,
+                            int64_t *graph_launches, int64_t *graph_captures) {
     if (!g) return eor::fail_status(EOR_ERR_ARG, "eor_group_tuning: group is NULL");
     if (stages) *stages = g->tune.stages;
     if (wg_per_cu) *wg_per_cu = g->tune.wg_per_cu;
+    if (tiles_per_pass) *tiles_per_pass = g->tune.tiles;
     if (graph_launches) *graph_launches = g->replays;
     if (graph_captures) *graph_captures = g->captures;
     return EOR_OK;
@@ -394,12 +411,13 @@ eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *the
     double best_ms = 1e300;
     eor_status st = EOR_OK;
     const int cand_stages[2] = {4, 2};
-    const int cand_wg[2] = {2, 1};
+    const int cand_shape[3][2] = {{1, 2}, {1, 1}, {2, 1}};  // (tiles per pass, workgroups per CU)
     for (int a = 0; a < 2 && st == EOR_OK; ++a) {
-        for (int b = 0; b < 2 && st == EOR_OK; ++b) {
+        for (int b = 0; b < 3 && st == EOR_OK; ++b) {
             eor::Tuning t;
             t.stages = cand_stages[a];
-            t.wg_per_cu = cand_wg[b];
+            t.tiles = cand_shape[b][0];
+            t.wg_per_cu = cand_shape[b][1];
             st = run_group(*g, B, theta, outs.data(), nullptr, t, false, s);  // warm-up
             float ms_sum = 0.f;
             for (int r = 0; r < 2 && st == EOR_OK; ++r) {
@@ -426,8 +444,8 @@ eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *the
     drop_graph(*g);
     if (cache_path) {
         std::ostringstream v;
-        v << "{\"stages\": " << best.stages << ", \"wg_per_cu\": " << best.wg_per_cu << ", \"ms\": " << best_ms
-          << "}";
+        v << "{\"stages\": " << best.stages << ", \"wg_per_cu\": " << best.wg_per_cu << ", \"tiles\": " << best.tiles
+          << ", \"ms\": " << best_ms << "}";
         cache[key] = v.str();
         if (!write_cache(cache_path, cache))
             return eor::fail_status(EOR_ERR_ARG, std::string("eor_autotune: cannot write ") + cache_path);

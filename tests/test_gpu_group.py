@@ -79,6 +79,38 @@ def test_group_equals_single_context(problem):
     g.close()
 
 
+def test_group_two_tiles_per_pass(problem):
+    """Eight-wave workgroups updating two tiles per pass: same bits as
+    four-wave workgroups, eager and from a graph."""
+    import paper_2501_12928_amd as eor
+    import torch
+    insts, ctxs, refs = problem
+    g = eor.Group(ctxs)
+    g.set_graph(False)
+    g.set_tuning(4, 2, 1)
+    base, _ = g.loglike(_thetas(insts))
+    torch.cuda.synchronize()
+    base = [b.clone() for b in base]
+    g.set_tuning(4, 1, 2)
+    assert g.tuning()[:3] == (4, 1, 2)
+    print("gpu: group, two tiles per pass", flush=True)
+    outs, infos = g.loglike(_thetas(insts))
+    torch.cuda.synchronize()
+    assert all(bool((i == 0).all()) for i in infos)
+    for a, b in zip(outs, base):
+        assert torch.equal(a, b)
+    g.set_graph(True)
+    outs, infos = g.loglike(_thetas(insts))
+    outs, infos = g.loglike(_thetas(insts), outs=outs, infos=infos)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, base):
+        assert torch.equal(a, b)
+    _check_all(outs, refs)
+    with pytest.raises(eor.EorError):
+        g.set_tuning(4, 2, 2)
+    g.close()
+
+
 def test_graph_replays_match_eager(problem):
     """The captured graph is replayed several times with unrelated eager
     work and synchronisations in between; every replay must equal the eager
@@ -93,7 +125,7 @@ def test_graph_replays_match_eager(problem):
     torch.cuda.synchronize()
     eager = [e.clone() for e in eager]
     g.set_graph(True)
-    _, _, launches0, captures0 = g.tuning()
+    launches0, captures0 = g.tuning()[3:]
     outs, infos = g.loglike(th)          # capture
     for r in range(4):
         print(f"gpu: graph replay {r}", flush=True)
@@ -105,7 +137,7 @@ def test_graph_replays_match_eager(problem):
         torch.cuda.synchronize()
         for a, b in zip(outs, eager):
             assert torch.equal(a, b)
-    _, _, launches, captures = g.tuning()
+    launches, captures = g.tuning()[3:]
     assert launches - launches0 == 5 and captures - captures0 == 1
     _check_all(eager, refs)
     g.close()
@@ -127,7 +159,7 @@ def test_graph_follows_new_buffers(problem):
         t.copy_(torch.from_numpy(v))
     outs, _ = g.loglike(th, outs=outs, infos=infos)     # same buffers: replay
     torch.cuda.synchronize()
-    assert g.tuning()[3] == 1
+    assert g.tuning()[4] == 1
     orc = oracle_get()
     refs2 = [orc.loglike_instance(i, theta=v)[0] for i, v in zip(insts, new)]
     _check_all(outs, refs2)
@@ -141,17 +173,17 @@ def test_autotune_and_cache(problem, tmp_path):
     cache = tmp_path / "tune.json"
     g = eor.Group(ctxs)
     print("gpu: autotune", flush=True)
-    st, wg = g.autotune(_thetas(insts), cache_path=cache)
-    assert st in (2, 4) and wg in (1, 2)
+    st, wg, tp = g.autotune(_thetas(insts), cache_path=cache)
+    assert (st, wg, tp) in [(s, w, p) for s in (2, 4) for (p, w) in ((1, 1), (1, 2), (2, 1))]
     data = json.loads(cache.read_text())
     key = [k for k in data if k.endswith("|n<=512|group")]
     assert len(key) == 1 and key[0].startswith("gfx950")
-    assert data[key[0]]["stages"] == st and data[key[0]]["wg_per_cu"] == wg
+    assert (data[key[0]]["stages"], data[key[0]]["wg_per_cu"], data[key[0]]["tiles"]) == (st, wg, tp)
     # a second group reads the cached choice (no timing)
-    data[key[0]] = {"stages": 2, "wg_per_cu": 1, "ms": 1.0}
+    data[key[0]] = {"stages": 2, "wg_per_cu": 1, "tiles": 2, "ms": 1.0}
     cache.write_text(json.dumps(data))
     g2 = eor.Group(ctxs)
-    assert g2.autotune(_thetas(insts), cache_path=cache)[:2] == (2, 1)
+    assert g2.autotune(_thetas(insts), cache_path=cache) == (2, 1, 2)
     outs, _ = g2.loglike(_thetas(insts))
     torch.cuda.synchronize()
     _check_all(outs, refs)

@@ -102,7 +102,46 @@ def test_terms_match_oracle(orc):
     np.testing.assert_allclose(terms[:, 3], c, rtol=1e-13)
 
 
-def test_failures_reported_per_theta(orc):
+# Launch choices (prefetch stages, workgroups per CU, tiles per pass).
+TUNINGS = [(4, 2, 1), (2, 2, 1), (4, 1, 1), (4, 1, 2), (2, 1, 2)]
+
+
+@pytest.mark.parametrize("m,n,n_k", [
+    (300, 130, 4),   # 3 tiles: 3, 2, 1 units per column
+    (520, 257, 5),   # 5 tiles, ragged by one
+    (900, 700, 6),   # 11 tiles
+])
+def test_launch_choices_agree(orc, m, n, n_k):
+    """Every launch choice meets the bar, and all give the same bits: the
+    tile updates sum in the same order whichever group computes them."""
+    inst = synth.small(seed=m + 3 * n, m=m, n=n, n_k=n_k, n_theta=12)
+    ref, rinfo = orc.loglike_instance(inst)
+    outs = []
+    for t in TUNINGS:
+        _say(f"gpu: n={n} tuning {t}")
+        got, info = run_instance(inst, tuning=t)
+        assert np.all(info == 0) and np.all(rinfo == 0)
+        _check(got, ref)
+        outs.append(got)
+    for t, o in zip(TUNINGS[1:], outs[1:]):
+        assert np.array_equal(o, outs[0]), t
+
+
+def test_tuning_arguments():
+    import paper_2501_12928_amd as eor
+    ctx = eor.Context(0)
+    assert ctx.tuning() == (4, 1, 2)
+    for bad in [(3, 1, 1), (4, 3, 1), (4, 2, 2), (4, 1, 3), (0, 0, 0)]:
+        with pytest.raises(eor.EorError):
+            ctx.set_tuning(*bad)
+    assert ctx.tuning() == (4, 1, 2)
+    ctx.set_tuning(2, 1, 2)
+    assert ctx.tuning() == (2, 1, 2)
+    ctx.close()
+
+
+@pytest.mark.parametrize("tuning", [None, (4, 2, 1)])
+def test_failures_reported_per_theta(orc, tuning):
     """Non-finite theta -> info -1; a NaN column of T -> pivot failure at
     that column (1-based), exactly as the oracle reports it; the rest of
     the batch is unaffected."""
@@ -112,8 +151,8 @@ def test_failures_reported_per_theta(orc):
     th[3, 0] = np.inf
     th[4, 1] = 400.0     # 10^400 overflows: prior variance not finite
     ref, rinfo = orc.loglike_instance(inst, theta=th)
-    _say("gpu: failure codes")
-    got, info = run_instance(inst, theta=th)
+    _say(f"gpu: failure codes, tuning {tuning}")
+    got, info = run_instance(inst, theta=th, tuning=tuning)
     np.testing.assert_array_equal(info, rinfo)
     np.testing.assert_array_equal(info, [0, -1, 0, -1, -1])
     assert np.all(got[info != 0] == -np.inf)
@@ -123,7 +162,7 @@ def test_failures_reported_per_theta(orc):
     bad.T = bad.T.copy()
     bad.T[:, 70] = np.nan
     ref, rinfo = orc.loglike_instance(bad)
-    got, info = run_instance(bad)
+    got, info = run_instance(bad, tuning=tuning)
     np.testing.assert_array_equal(rinfo, [71, 71, 71])
     np.testing.assert_array_equal(info, rinfo)
     assert np.all(got == -np.inf)
@@ -170,25 +209,26 @@ def test_one_bin_eigen_closed_form():
     _check(got, ref)
 
 
-def _sampled(config_id):
+def _sampled(config_id, tuning=None):
     path = os.path.join(GOLDEN, f"c{config_id}_oracle_sample.json")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     g = json.load(open(path))
     inst = synth.gen(config_id)
     assert inst.digest() == g["digest"], "synthetic inputs differ from the ones the oracle saw"
-    _say(f"gpu: full workload {config_id}: m={inst.m} n={inst.n} B={inst.theta.shape[0]}")
-    got, info = run_instance(inst)
+    _say(f"gpu: full workload {config_id}: m={inst.m} n={inst.n} B={inst.theta.shape[0]} tuning {tuning}")
+    got, info = run_instance(inst, tuning=tuning)
     idx = np.array(g["index"])
     assert np.all(info == 0)
     _check(got[idx], np.array(g["logL"]))
     assert np.all(np.isfinite(got))
 
 
-def test_plain_batched_workload_sampled():
+@pytest.mark.parametrize("tuning", [None, (4, 2, 1)])
+def test_plain_batched_workload_sampled(tuning):
     """8000 x 2048, 8 bins, B = 256 in one call; 16 theta checked against
     oracle values stored by tests/golden/make_golden.py."""
-    _sampled(1)
+    _sampled(1, tuning)
 
 
 @pytest.mark.slow
