@@ -70,6 +70,15 @@ __device__ inline d4 mfma64(double a, double b, d4 c) {
 // different waves then execute different numbers of barriers.
 __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Hides a lane-dependent value from loop-invariant code motion: addresses
+// derived from it are formed where they are used instead of being hoisted
+// out of the column loop, where they would stay live (and spill) across
+// every tile update.
+__device__ inline int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 template <class T>
 __device__ inline T *uniform_ptr(T *p) {
     const uint64_t v = (uint64_t)p;
@@ -204,7 +213,6 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
     const int w = uniform((tid >> 6) & 3);   // row slab 16w..16w+15 of the group's tile
     const int grp = uniform(tid >> 8);       // group within the workgroup
     const int voff = (q * TS + l16) * 16;    // lane offset of operand loads (bytes)
-    const int voff_st = (l16 * TS + q) * 16; // lane offset of L_ij stores (bytes): Y[16w + q][l16]
     double2 *L = uniform_ptr(a.Lw + (int64_t)blockIdx.x * a.slot_tiles * TS2);
     double2 *yv = uniform_ptr(a.yw + (int64_t)blockIdx.x * a.slot_y);
 
@@ -277,30 +285,32 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                     tile_update<STAGES>(Ar, Pr, Qr, K, voff, xr, xi);
                 } else {
                     panel_barriers(K);  // no tile for this group in the last round
+                    // Defined on this path too: otherwise the compiler carries the
+                    // previous round's values across the loop (64 live registers).
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) xr[cb] = xi[cb] = d4{0, 0, 0, 0};
                 }
                 if (u == 0) {
-                    // D = X + diag(Phi^{-1}) -> LDS (column-major)
-                    const int lo = q * TS + 16 * w + l16;  // [16w + l16][q]
-                    const int dq = l16 - q;                // row == col iff cb == w, 4r == dq
-                    const int row = 16 * w + l16;
+                    // X of the diagonal tile -> LDS (column-major)
+                    const int lo = opaque(q * TS + 16 * w + l16);  // [16w + l16][q]
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            double2 v = make_double2(xr[cb][r], xi[cb][r]);
-                            if (cb == w && dq == 4 * r) {
-                                const int64_t g = (int64_t)j * TS + row;
-                                const int32_t b = I.coef_bin[g];
-                                const double ip = b >= 0 ? 1.0 / (I.bin_scale[b] * exp10(th[b])) : I.coef_inv[g];
-                                v.x += ip;
-                            }
-                            Dt[lo + (16 * cb + 4 * r) * TS] = v;
-                        }
+                        for (int r = 0; r < 4; ++r) Dt[lo + (16 * cb + 4 * r) * TS] = make_double2(xr[cb][r], xi[cb][r]);
                     }
                     if (tid < TS) wv[tid] = yv[(int64_t)j * TS + tid];
                 }
 
                 if (u0 == 0) {
+                    const int tid = opaque(threadIdx.x);
+                    // ---- D = X + diag(Phi^{-1}) ------------------------------------
+                    __syncthreads();
+                    if (tid < TS) {
+                        const int64_t g = (int64_t)j * TS + tid;
+                        const int32_t b = I.coef_bin[g];
+                        const double ip = b >= 0 ? 1.0 / (I.bin_scale[b] * exp10(th[b])) : I.coef_inv[g];
+                        Dt[tid * TS + tid].x += ip;
+                    }
                     // ---- Cholesky of the diagonal tile in LDS (right-looking)
                     // Column c is left unscaled during the sweep; the update uses
                     // D[r][s] -= D[r][c] conj(D[s][c]) / D[c][c].
@@ -395,6 +405,7 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                 }
 
                 if (u > 0 && u < units) {
+                    const int lane = opaque(threadIdx.x & 63), l16 = lane & 15, q = lane >> 4;
                     // ---- L_ij = X Linv^H; w_i -= L_ij y_j -----------------------
                     // Y[i][c'] = sum_c X[i][c] conj(Linv[c'][c]); Linv is lower
                     // triangular, so output block cb2 needs column blocks cb <= cb2.
@@ -402,7 +413,7 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                     // raw buffer stores, tiles read by the other group in later
                     // columns came back stale now and then (no fault), which plain
                     // stores have never shown.
-                    double2 *Lij = L + tile_index(i, j) * TS2 + voff_st / 16 + 16 * w;
+                    double2 *Lij = L + tile_index(i, j) * TS2 + l16 * TS + 16 * w + q;  // Y[16w + q][l16]
                     const int lt = q * TS + l16;  // Linv[l16][q] in LDS
                     double wr[4] = {0, 0, 0, 0}, wi[4] = {0, 0, 0, 0};
 #pragma unroll
