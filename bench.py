@@ -74,11 +74,55 @@ def cpu_baseline(inst, n_rows: int = 2000):
     t_like = time.perf_counter() - t0
     B = inst.theta.shape[0]
     step_s = t_pre + t_like * (B / th.shape[0])
-    return {"value": B / step_s, "unit": "evals/s", "cores": threads, "kind": "oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": B / step_s, "unit": "evals/s", "cores": threads, "kind": "oracle", "cpu_model": model,
             "sample": (f"precompute over {rows} of {inst.m} rows (time scaled x{inst.m / rows:g}) + "
                        f"{th.shape[0]} theta at n={inst.n} in parallel (one per thread), scaled to "
                        f"B={B}; plain C FP64 oracle, OpenMP"),
             "seconds_measured": round(t_pre * rows / inst.m + t_like, 2)}
+
+
+def cpu_lapack_reference(ctx, inst, per_n=((4096, 2), (2048, 4))):
+    """A stronger CPU reference than the oracle (not the baseline): LAPACK's
+    blocked Cholesky (scipy, multithreaded BLAS) plus the triangular solve and
+    log-determinant, on Sigma = A + Phi^-1 built from the GPU path's exported
+    A. Timing only; the n = 2048 case uses A's leading block."""
+    import numpy as np
+    import scipy.linalg as sl
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [x for x in threadpool_info() if x.get("user_api") == "blas"]
+        threads = blas[0]["num_threads"] if blas else None
+        lib = f"{blas[0]['internal_api']} {blas[0]['version']}" if blas else "unknown"
+    except Exception:
+        threads, lib = None, "unknown"
+    A, dbar, c, K0 = ctx.export_precompute()
+    A = A.cpu().numpy()
+    dbar = dbar.cpu().numpy()
+    rep = {"kind": "lapack zpotrf + ztrsv via scipy", "blas": lib, "threads": threads, "unit": "evals/s"}
+    for n, k in per_n:
+        n = min(n, A.shape[0])
+        best = []
+        for t in range(k):
+            th = inst.theta[t]
+            b = inst.bin_of[:n]
+            phi = np.where(b >= 0, inst.bin_scale[np.maximum(b, 0)] * 10.0 ** th[np.maximum(b, 0)],
+                           inst.fixed_var[:n])
+            t0 = time.perf_counter()
+            S = A[:n, :n].copy()
+            S[np.diag_indices(n)] += 1.0 / phi
+            L = sl.cholesky(S, lower=True, check_finite=False)
+            y = sl.solve_triangular(L, dbar[:n], lower=True, check_finite=False)
+            _ = 2.0 * np.sum(np.log(np.real(np.diag(L)))) + np.vdot(y, y).real
+            best.append(time.perf_counter() - t0)
+        rep[f"n{n}"] = 1.0 / float(np.median(best))
+    rep["value"] = rep.get(f"n{min(4096, A.shape[0])}")
+    return rep
 
 
 def precision_report(ctx, inst, T, nv, d, theta, logL64):
@@ -107,9 +151,11 @@ def precision_report(ctx, inst, T, nv, d, theta, logL64):
         rel = (torch.linalg.norm(A - A64).item()) / nrm
         del A
         L, info = ctx.loglike_batch(theta)
-        dl = (L - logL64).abs()
-        rep[prec] = {"rel_frob_A": rel, "max_abs_dlogL": dl.max().item(),
-                     "max_rel_dlogL": (dl / logL64.abs()).max().item(),
+        both = (info == 0) & torch.isfinite(logL64)
+        dl = (L - logL64).abs()[both]
+        rep[prec] = {"rel_frob_A": rel,
+                     "max_abs_dlogL": dl.max().item() if dl.numel() else None,
+                     "max_rel_dlogL": (dl / logL64.abs()[both]).max().item() if dl.numel() else None,
                      "precompute_ms": ms, "info_nonzero": int((info != 0).sum().item())}
     del A64
     ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, prec="fp64")
@@ -177,6 +223,42 @@ def bench_group(args):
         c.close()
 
 
+def bench_stress(args):
+    """Precision under ill-conditioning (reported, not a metric): T with
+    singular values over four decades at 8000 x 2048, with the usual
+    foreground share and with a wide-field foreground model (n_fg = 1792 >>
+    n_eor = 256). For each, the FP64 path's failures and time, and what FP32
+    and split-BF16 A do to positive definiteness and to logL."""
+    import torch
+    import synth
+    import paper_2501_12928_amd as eor
+    out = {"metric": "precision under ill-conditioned instruments (report)", "n_gpus": 1,
+           "dtype": "f64 (A also in f32 and split bf16)", "data": "synthetic", "variants": {}}
+    for name in sorted(synth.STRESS):
+        print(f"stress: {name}", file=sys.stderr, flush=True)
+        inst = synth.gen_stress(name)
+        T = torch.from_numpy(inst.T).cuda()
+        nv = torch.from_numpy(inst.noise_var).cuda()
+        d = torch.from_numpy(inst.d).cuda()
+        theta = torch.from_numpy(inst.theta).cuda()
+        ctx = eor.Context(0)
+        ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale)
+        L64, info64 = ctx.loglike_batch(theta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.loglike_batch(theta, out=L64, info=info64)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        rep = precision_report(ctx, inst, T, nv, d, theta, L64.clone())
+        rep["fp64_info_nonzero"] = int((info64 != 0).sum().item())
+        rep["fp64_loglike_ms"] = ms
+        rep["shape"] = {k: v for k, v in synth.STRESS[name].items()}
+        out["variants"][name] = rep
+        ctx.close()
+        del T, nv, d, theta
+    print(json.dumps(out))
+
+
 def bench_gated(args):
     """Nested sampling on the 12-bin n = 4096 dataset, once with every
     proposal evaluated exactly and once gated by the surrogate ensemble
@@ -222,9 +304,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
-    ap.add_argument("--workload", choices=["metric", "group", "gated"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress"], default="metric",
                     help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances; "
-                         "gated: nested sampling at 20000x4096 without and with the surrogate gate")
+                         "gated: nested sampling at 20000x4096 without and with the surrogate gate; "
+                         "stress: reduced precision on ill-conditioned instruments at 8000x2048")
     ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
     ap.add_argument("--n-live", type=int, default=500)
     ap.add_argument("--first-train", type=int, default=30000)
@@ -266,6 +349,8 @@ def main():
         return bench_group(args)
     if args.workload == "gated":
         return bench_gated(args)
+    if args.workload == "stress":
+        return bench_stress(args)
 
     inst = synth.gen(CONFIG_ID)
     B, n, m = inst.theta.shape[0], inst.n, inst.m
@@ -338,6 +423,7 @@ def main():
         out["precision"] = precision_report(ctx, inst, T, nv, d, theta, logL.clone())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst)
+        out["cpu_lapack"] = cpu_lapack_reference(ctx, inst)
     else:
         out["cpu_baseline"] = None
     ctx.close()

@@ -182,5 +182,30 @@ def stress_T(rng: np.random.Generator, m: int, n: int, decades: float = 4.0) -> 
     return np.ascontiguousarray((U * s[None, :]) @ V.conj().T)
 
 
+def stress(seed: int, m: int, n: int, n_k: int, n_eor: int | None = None, n_theta: int = 8,
+           lo: float = -1.0, hi: float = 3.0, decades: float = 4.0) -> Instance:
+    """Instance with the ill-conditioned instrument matrix of stress_T."""
+    rng = np.random.default_rng(seed)
+    T = stress_T(rng, m, n, decades)
+    return make_instance(rng, m=m, n=n, n_k=n_k,
+                         n_eor=n - n // 8 if n_eor is None else n_eor,
+                         n_theta=n_theta, lo=lo, hi=hi, T=T)
+
+
+# Stress workloads at the plain-batched sizes (reported, not a metric):
+# singular values of T over four decades, and a wide-field foreground model
+# with many more foreground than EoR coefficients on the same T.
+STRESS = {
+    "svd4": dict(m=8000, n=2048, n_k=8, n_eor=1792, n_theta=256, decades=4.0),
+    "widefg": dict(m=8000, n=2048, n_k=8, n_eor=256, n_theta=256, decades=4.0),
+}
+
+
+def gen_stress(name: str, seed: int | None = None) -> Instance:
+    cfg = dict(STRESS[name])
+    base = 2000 + sorted(STRESS).index(name)
+    return stress(base if seed is None else seed, **cfg)
+
+
 def theta_batch(rng: np.random.Generator, B: int, n_k: int, lo: float, hi: float) -> np.ndarray:
     return np.ascontiguousarray(rng.uniform(lo, hi, size=(B, n_k)))

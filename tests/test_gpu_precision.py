@@ -79,3 +79,45 @@ def test_reduced_precision_loglike(orc, prec):
     err = np.abs(got - ref)
     bound = np.maximum(tol(ref), 20.0 * np.abs(emul - ref))
     assert np.all(err <= bound), (err.max(), np.abs(emul - ref).max())
+
+
+# Ill-conditioned inputs: T with singular values over four decades, with the
+# usual foreground share and with a wide-field foreground model (far more
+# foreground than EoR coefficients).
+STRESS_CASES = {
+    "svd4": dict(m=700, n=300, n_k=3),
+    "widefg": dict(m=700, n=300, n_k=3, n_eor=40),
+}
+
+
+@pytest.mark.parametrize("case", sorted(STRESS_CASES))
+def test_stress_fp64_matches_oracle(orc, case):
+    inst = synth.stress(seed=31 + len(case), n_theta=8, **STRESS_CASES[case])
+    ref, rinfo = orc.loglike_instance(inst)
+    print(f"gpu: stress {case} fp64", flush=True)
+    got, info = run_instance(inst)
+    np.testing.assert_array_equal(info, rinfo)
+    ok = info == 0
+    assert ok.any()
+    assert np.all(np.abs(got[ok] - ref[ok]) <= tol(ref[ok])), np.max(np.abs(got[ok] - ref[ok]))
+    assert np.all(got[~ok] == -np.inf)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", sorted(STRESS_CASES))
+def test_stress_reduced_precision_reports_cleanly(orc, case, prec):
+    """A reduced-precision A may lose positive definiteness on ill-conditioned
+    inputs (the reason the factorisation stays FP64). Whatever happens, each
+    theta either factors (finite logL, info 0) or reports its failing pivot
+    (info in 1..n, logL = -inf); nothing non-finite escapes otherwise."""
+    inst = synth.stress(seed=31 + len(case), n_theta=8, **STRESS_CASES[case])
+    ref, _ = orc.loglike_instance(inst)
+    print(f"gpu: stress {case} {prec}", flush=True)
+    got, info = run_instance(inst, prec=prec)
+    assert np.all((info == 0) | ((info >= 1) & (info <= inst.n)))
+    assert np.all(np.isfinite(got[info == 0]))
+    assert np.all(got[info != 0] == -np.inf)
+    ok = info == 0
+    if ok.any():
+        print(f"  {case} {prec}: {int((~ok).sum())} of {info.size} failed; max |dlogL| "
+              f"{np.max(np.abs(got[ok] - ref[ok])):.3g}", flush=True)
