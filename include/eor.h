@@ -82,8 +82,9 @@ void eor_destroy(eor_ctx *ctx);
  * Once-per-dataset precompute: A = T^H N^{-1} T (stored in FP64 whatever
  * `prec`), dbar = T^H N^{-1} d, c = d^H N^{-1} d and the constant terms of
  * logL.
- *   m, n       rows and columns of T (m >= 1, 1 <= n <= 65536)
- *   T          device, complex128, row-major m x n with row stride ldT >= n
+ *   m, n       rows and columns of T (1 <= m <= 2^28, 1 <= n <= 65536)
+ *   T          device, complex128, row-major m x n with row stride
+ *              n <= ldT <= 2^24
  *   noise_var  device [m], sigma_i^2; must be > 0 (not checked on the device)
  *   d          device complex128 [m]
  *   n_k        number of k-bins (>= 0)

@@ -193,8 +193,10 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
                           const double *fixed_var, const double *bin_scale, eor_precision prec,
                           void *stream) {
     if (!ctx) return fail(EOR_ERR_ARG, "eor_precompute: ctx is NULL");
-    if (m < 1 || n < 1 || n > 65536) return fail(EOR_ERR_ARG, "eor_precompute: need m >= 1 and 1 <= n <= 65536");
+    if (m < 1 || m > ((int64_t)1 << 28) || n < 1 || n > 65536)
+        return fail(EOR_ERR_ARG, "eor_precompute: need 1 <= m <= 2^28 and 1 <= n <= 65536");
     if (ldT < n) return fail(EOR_ERR_ARG, "eor_precompute: ldT < n");
+    if (ldT > ((int64_t)1 << 24)) return fail(EOR_ERR_ARG, "eor_precompute: ldT > 2^24");
     if (!T || !noise_var || !d || !bin_of) return fail(EOR_ERR_ARG, "eor_precompute: NULL array");
     if (n_k < 0 || n_k > 4096) return fail(EOR_ERR_ARG, "eor_precompute: need 0 <= n_k <= 4096");
     if (prec != EOR_PREC_FP64 && prec != EOR_PREC_FP32 && prec != EOR_PREC_BF16X3)
@@ -292,18 +294,20 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     EOR_TRY(eor::launch_precompute_vectors(c, Td, ldT, noise_var, (const double2 *)d, c.invvar, c.partial,
                                            c.splits, s),
             "precompute vectors");
-    if (prec != EOR_PREC_FP64) {
-        const size_t need = eor::lowp_scratch_bytes(prec, m, c.n_pad);
+    {
+        // precompute scratch: partial tiles of a row-split FP64 product, or W in reduced precision
+        const size_t need = prec == EOR_PREC_FP64 ? eor::herk_scratch_bytes(m, N, c.num_cu)
+                                                  : eor::lowp_scratch_bytes(prec, m, c.n_pad);
         if (c.lowp_bytes < need) {
             if (c.lowp) (void)hipFree(c.lowp);
             c.lowp = nullptr;
             c.lowp_bytes = 0;
-            EOR_TRY(hipMalloc(&c.lowp, need), "hipMalloc reduced-precision W");
+            EOR_TRY(hipMalloc(&c.lowp, need), "hipMalloc precompute scratch");
             c.lowp_bytes = need;
         }
     }
     if (prec == EOR_PREC_FP64)
-        EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, c.invvar, s), "precompute A (fp64)");
+        EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (fp64)");
     else if (prec == EOR_PREC_FP32)
         EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (fp32)");
     else

@@ -106,7 +106,7 @@ struct Context {
     double *h_scale = nullptr;
     int32_t *h_count = nullptr;
     InstDesc *h_inst = nullptr;
-    void *lowp = nullptr;        // W in FP32 or in split BF16 planes (reduced-precision A)
+    void *lowp = nullptr;        // precompute scratch: FP64 partial tiles, or W in FP32 / split BF16
     size_t lowp_bytes = 0;
     int64_t alloc_m = 0, alloc_n = 0;
     int32_t alloc_k = -1;
@@ -129,8 +129,9 @@ inline bool valid_tuning(int stages, int wg_per_cu, int tiles) {
 }
 
 // Kernel launchers (precompute.hip, likelihood.hip).
+size_t herk_scratch_bytes(int64_t m, int64_t N, int num_cu);
 hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ldT,
-                                  const double *invvar, hipStream_t s);
+                                  const double *invvar, void *scratch, hipStream_t s);
 size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad);
 hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ldT,
                                   const double *invvar, void *scratch, hipStream_t s);
