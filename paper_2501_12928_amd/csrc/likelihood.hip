@@ -54,6 +54,7 @@ namespace {
 constexpr int GROUP_THREADS = 256;  // one group: 4 waves of 64, each owning 16 rows of a tile
 constexpr int TILE_BYTES = TS2 * 16;
 constexpr int COL_BYTES = TS * 16;  // one column of a tile (or of a panel)
+constexpr int TRI_SPLIT = 4;        // waves that share each dot product of the triangular inverse
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -207,6 +208,7 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
     __shared__ double2 ys[TS];    // y_j
     __shared__ double dg[TS];     // pivots of the current diagonal tile
     __shared__ double red[TS];    // |y_j|^2 per row
+    __shared__ double2 part[TRI_SPLIT][TS];  // partial sums of the triangular inverse
     __shared__ int task_sh;
 
     const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
@@ -364,23 +366,36 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                     // Columns from the last to the first:
                     //   Linv[c][c] = 1 / L[c][c]
                     //   Linv[r][c] = -(sum_{k=c+1..r} Linv[r][k] L[k][c]) / L[c][c],  r > c
+                    // Each sum is split over the four waves of group 0 (lane = row,
+                    // wave p takes k = c+1+p, c+5+p, ...) and the four partials are
+                    // added in a fixed order, so the result does not depend on G.
                     for (int c = TS - 1; c >= 0; --c) {
-                        double2 nv = make_double2(0.0, 0.0);
-                        const int r = tid;
-                        const double lcc = Dt[c * TS + c].x;
-                        if (r < TS && r > c) {
+                        const int r = tid & 63, p = tid >> 6;
+                        if (p < TRI_SPLIT) {
                             double sr = 0.0, si = 0.0;
-                            for (int k = c + 1; k <= r; ++k) {
+                            for (int k = c + 1 + p; k <= r; k += TRI_SPLIT) {
                                 const double2 x = Dt[k * TS + r];  // Linv[r][k] (already inverted)
                                 const double2 l = Dt[c * TS + k];  // L[k][c]
                                 sr += x.x * l.x - x.y * l.y;
                                 si += x.x * l.y + x.y * l.x;
                             }
-                            nv = make_double2(-sr / lcc, -si / lcc);
+                            part[p][r] = make_double2(sr, si);
                         }
                         __syncthreads();
-                        if (r < TS && r > c) Dt[c * TS + r] = nv;
-                        if (r == c) Dt[c * TS + c] = make_double2(1.0 / lcc, 0.0);
+                        if (tid < TS) {
+                            const double lcc = Dt[c * TS + c].x;
+                            if (r > c) {
+                                double2 acc = part[0][r];
+#pragma unroll
+                                for (int pp = 1; pp < TRI_SPLIT; ++pp) {
+                                    acc.x += part[pp][r].x;
+                                    acc.y += part[pp][r].y;
+                                }
+                                Dt[c * TS + r] = make_double2(-acc.x / lcc, -acc.y / lcc);
+                            } else if (r == c) {
+                                Dt[c * TS + c] = make_double2(1.0 / lcc, 0.0);
+                            }
+                        }
                         __syncthreads();
                     }
 
