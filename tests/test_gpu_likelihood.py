@@ -236,3 +236,44 @@ def test_metric_workload_sampled():
     """20000 x 4096, 12 bins, B = 512 in one call (the benchmark's launch);
     8 theta checked against stored oracle values."""
     _sampled(3)
+
+
+def test_largest_shape_block_rotation():
+    """n = 8192 (128 tiles per side), beyond any shape the oracle finishes
+    quickly, through a property that holds at any size: two independent
+    4096-coefficient problems with the same bins, stacked block-diagonally and
+    then mixed pair by pair (coefficient j of each with a random 2 x 2
+    unitary; both have the same prior variance, so the likelihood is
+    unchanged while A becomes dense), must give the sum of the two logL. The
+    4096-coefficient path is itself held to the oracle elsewhere."""
+    rng = np.random.default_rng(8192)
+    n1, m1, n_k, n_eor = 4096, 4400, 6, 3584
+    p1 = synth.make_instance(rng, m=m1, n=n1, n_k=n_k, n_eor=n_eor, n_theta=4, lo=-1.0, hi=3.0)
+    p2 = synth.make_instance(rng, m=m1, n=n1, n_k=n_k, n_eor=n_eor, n_theta=4, lo=-1.0, hi=3.0)
+    assert np.array_equal(p1.bin_of, p2.bin_of)
+    n, m = 2 * n1, 2 * m1
+    T = np.zeros((m, n), dtype=np.complex128)
+    # pair rotation: columns j and j + n1 of blockdiag(T1, T2) mixed by U_j
+    a = rng.standard_normal(n1) + 1j * rng.standard_normal(n1)
+    b = rng.standard_normal(n1) + 1j * rng.standard_normal(n1)
+    nrm = np.sqrt(np.abs(a) ** 2 + np.abs(b) ** 2)
+    a, b = a / nrm, b / nrm
+    # U_j = [[a, -conj(b)], [b, conj(a)]] (unitary); T' = blockdiag(T1, T2) U
+    T[:m1, :n1] = p1.T * a[None, :]
+    T[m1:, :n1] = p2.T * b[None, :]
+    T[:m1, n1:] = p1.T * (-np.conj(b))[None, :]
+    T[m1:, n1:] = p2.T * np.conj(a)[None, :]
+    big = synth.Instance(T=T, noise_var=np.concatenate([p1.noise_var, p2.noise_var]),
+                         d=np.concatenate([p1.d, p2.d]), n_k=n_k,
+                         bin_of=np.concatenate([p1.bin_of, p2.bin_of]),
+                         fixed_var=np.concatenate([p1.fixed_var, p2.fixed_var]),
+                         bin_scale=p1.bin_scale, theta=p1.theta, theta_true=p1.theta_true,
+                         lo=p1.lo, hi=p1.hi)
+    _say("gpu: n=4096 halves")
+    l1, i1 = run_instance(p1)
+    l2, i2 = run_instance(p2, theta=p1.theta)
+    _say("gpu: n=8192 mixed, 4 theta (about 2.5 s each on one CU)")
+    lb, ib = run_instance(big)
+    assert np.all(i1 == 0) and np.all(i2 == 0) and np.all(ib == 0)
+    ref = l1 + l2
+    assert np.all(np.abs(lb - ref) <= tol(ref)), np.max(np.abs(lb - ref))
