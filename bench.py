@@ -274,11 +274,18 @@ def bench_gated(args):
                    torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
     sur = eor.Surrogate(inst.n_k, inst.lo, inst.hi, n_members=5, hidden=256, seed=1)
     cfg = eor.train_cfg(epochs=args.train_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=5)
+    # Warm retraining gets the first training's budget by default: with a short
+    # one the members stay close to their common starting point, agree with each
+    # other (small spread) and are wrong together, which the audits show as
+    # false rejections.
+    rcfg = None if args.retrain_epochs is None else eor.train_cfg(
+        epochs=args.retrain_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=6)
     plain, gated, cmp = run_plain_and_gated(ctx, inst.n_k, inst.lo, inst.hi, sur, n_live=args.n_live, seed=7,
                                             tau=args.tau, first_train=args.first_train,
                                             retrain_every=args.retrain_every, window=args.window,
                                             margin=args.margin, train_cfg=cfg, batch=512, dlogz=0.01,
-                                            audit_frac=0.01, pool_factor=args.pool_factor, progress=2000)
+                                            audit_frac=0.01, pool_factor=args.pool_factor, progress=2000,
+                                            retrain_cfg=rcfg)
     m, sd = gated.posterior_moments()
     print(json.dumps({
         "metric": "proposals judged per second by nested sampling at n=4096 complex FP64, surrogate-gated",
@@ -286,9 +293,10 @@ def bench_gated(args):
         "higher_is_better": True, "dtype": "f64 likelihood, f32 surrogate", "data": "synthetic",
         "config": {"workload": f"T complex128 {inst.m}x{inst.n}, {inst.n_k} k-bins, n_live={args.n_live}, "
                                f"gate tau={args.tau}, first training after {args.first_train} exact "
-                               f"evaluations, retrain every {args.retrain_every} iterations on the last "
-                               f"{args.window} within {args.margin} of the threshold, pools of "
-                               f"{args.pool_factor} x 512 proposals"},
+                               f"evaluations ({args.train_epochs} epochs), retrain every {args.retrain_every} "
+                               f"iterations on the last {args.window} within {args.margin} of the threshold "
+                               f"({args.retrain_epochs or args.train_epochs} epochs, warm), exact calls of "
+                               f"512 proposals the gate is unsure of"},
         "plain_proposals_per_s": plain.n_proposed / plain.wall_s,
         "comparison": cmp,
         "posterior_mean": m.tolist(), "posterior_std": sd.tolist(),
@@ -311,12 +319,14 @@ def main():
     ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
     ap.add_argument("--n-live", type=int, default=500)
     ap.add_argument("--first-train", type=int, default=30000)
-    ap.add_argument("--retrain-every", type=int, default=2000)
+    ap.add_argument("--retrain-every", type=int, default=5000)
     ap.add_argument("--window", type=int, default=8000)
     ap.add_argument("--tau", type=float, default=0.05)
     ap.add_argument("--margin", type=float, default=10.0)
-    ap.add_argument("--train-epochs", type=int, default=400)
-    ap.add_argument("--train-minibatch", type=int, default=256)
+    ap.add_argument("--train-epochs", type=int, default=300)
+    ap.add_argument("--retrain-epochs", type=int, default=None,
+                    help="epochs of each warm retraining (default: as the first training)")
+    ap.add_argument("--train-minibatch", type=int, default=512)
     ap.add_argument("--pool-factor", type=int, default=1)
     ap.add_argument("--tuning", default=None,
                     help="launch choices 'stages,wg_per_cu,tiles_per_pass' of the likelihood batch "

@@ -125,14 +125,12 @@ class NestedSampler:
             self.gate.observe(th, L)
         return L
 
-    def _propose(self, live):
-        """A pool of proposals inside the prior box from the live points'
-        enlarged bounding ellipsoid: one exact batch without a trained gate,
-        pool_factor batches with one (the surrogate screens them cheaply)."""
+    def _propose(self, live, count):
+        """`count` proposals inside the prior box from the live points'
+        enlarged bounding ellipsoid."""
         ell = Ellipsoid(live, self.enlarge)
         out = []
-        gated = self.gate is not None and self.gate.trained
-        need = self.batch * (self.pool_factor if gated else 1)
+        need = count
         while need > 0:
             x = ell.sample(self.rng, max(need * 2, 64))
             x = x[np.all((x >= self.lo) & (x <= self.hi), axis=1)]
@@ -140,23 +138,46 @@ class NestedSampler:
             need -= out[-1].shape[0]
         return np.concatenate(out)
 
-    def _new_pool(self, live):
-        """A pool of proposals: exact logL evaluated now (no gate, or an
-        untrained one) or left for later (NaN) with the surrogate's mean and
-        spread attached."""
-        th = self._propose(live)
-        self.stats["n_proposed"] += th.shape[0]
-        pool = {"th": th, "L": np.full(th.shape[0], np.nan), "mean": None, "spread": None, "pos": 0}
-        pred = None
-        if self.gate is not None:
-            t0 = time.perf_counter()
-            pred = self.gate.predict(th)
-            self.stats["t_gate"] += time.perf_counter() - t0
-        if pred is None:
+    def _new_pool(self, live, L_min):
+        """A pool of proposals. Without a trained gate: one batch, evaluated
+        exactly now. With one: proposals are drawn and screened by the
+        surrogate until the pool holds `batch` that it is unsure of at the
+        current threshold (at most pool_factor x 8 batches), and the pool ends
+        at that one; so the exact call it leads to fills whole rounds of the
+        GPU, while the proposals stay an i.i.d. sequence consumed in order
+        (the cut is a stopping time). Exact logL are left for later (NaN)."""
+        gated = self.gate is not None and self.gate.trained
+        if not gated:
+            th = self._propose(live, self.batch)
+            self.stats["n_proposed"] += th.shape[0]
+            pool = {"th": th, "L": np.full(th.shape[0], np.nan), "mean": None, "spread": None, "pos": 0}
             pool["L"][:] = self._exact(th)
-        else:
-            pool["mean"], pool["spread"] = pred
-        return pool
+            return pool
+        ths, means, spreads = [], [], []
+        unsure = 0
+        cap = self.batch * self.pool_factor * 8
+        drawn = 0
+        while unsure < self.batch and drawn < cap:
+            th = self._propose(live, self.batch * self.pool_factor)
+            t0 = time.perf_counter()
+            m, sp = self.gate.predict(th)
+            self.stats["t_gate"] += time.perf_counter() - t0
+            u = ~((sp <= self.gate.tau) & (m < L_min))
+            c = np.cumsum(u)
+            if unsure + int(c[-1]) >= self.batch:
+                cut = int(np.searchsorted(c, self.batch - unsure)) + 1
+                th, m, sp = th[:cut], m[:cut], sp[:cut]
+                unsure = self.batch
+            else:
+                unsure += int(c[-1])
+            ths.append(th)
+            means.append(m)
+            spreads.append(sp)
+            drawn += th.shape[0]
+        th = np.concatenate(ths)
+        self.stats["n_proposed"] += th.shape[0]
+        return {"th": th, "L": np.full(th.shape[0], np.nan), "mean": np.concatenate(means),
+                "spread": np.concatenate(spreads), "pos": 0}
 
     def _confident_reject(self, pool, i, L_min):
         return (pool["mean"] is not None and pool["spread"][i] <= self.gate.tau
@@ -178,13 +199,11 @@ class NestedSampler:
                 pool["pos"] += 1
                 self.stats["n_gate_rejected"] += 1
                 if self.audit_frac > 0 and self.audit_rng.uniform() < self.audit_frac:
-                    La = float(self._exact(th[i:i + 1])[0])
-                    self.stats["n_audited"] += 1
-                    self.stats["n_false_reject"] += int(La > L_min)
+                    self._audits.append((th[i].copy(), L_min))  # judged in full batches at the end
                 continue
-            # evaluate exactly the next batch of proposals the gate is unsure of
+            # evaluate exactly, in one call, the rest of the pool that the gate is unsure of
             idx = [j for j in range(i, th.shape[0])
-                   if np.isnan(L[j]) and not self._confident_reject(pool, j, L_min)][:self.batch]
+                   if np.isnan(L[j]) and not self._confident_reject(pool, j, L_min)]
             L[idx] = self._exact(th[idx])
         return None
 
@@ -197,6 +216,7 @@ class NestedSampler:
         logz = -np.inf
         ln_x_prev = 0.0
         pool = None
+        self._audits = []
         it = 0
         t_train0 = self.gate.train_seconds if self.gate is not None else 0.0
         while it < self.max_iter:
@@ -213,7 +233,7 @@ class NestedSampler:
             # replacement: the next pooled proposal above the threshold
             j = None if pool is None else self._next_valid(pool, L_min)
             while j is None:
-                pool = self._new_pool(live)
+                pool = self._new_pool(live, L_min)
                 j = self._next_valid(pool, L_min)
             live[worst] = pool["th"][j]
             live_L[worst] = pool["L"][j]
@@ -227,6 +247,13 @@ class NestedSampler:
             # stop when the live points can no longer change ln Z by dlogz
             if np.logaddexp(logz, float(np.max(live_L)) + ln_x) - logz < self.dlogz:
                 break
+        # audits of gate rejections: exact logL against the threshold in force
+        # when each was rejected (they change nothing in the run)
+        for a in range(0, len(self._audits), self.batch):
+            chunk = self._audits[a:a + self.batch]
+            La = self._exact(np.stack([t for t, _ in chunk]))
+            self.stats["n_audited"] += len(chunk)
+            self.stats["n_false_reject"] += int(sum(v > lm for v, (_, lm) in zip(La, chunk)))
         # the final live points share the remaining prior volume
         ln_wl = live_L + ln_x_prev - math.log(n)
         logz_final = np.logaddexp(logz, np.logaddexp.reduce(ln_wl))
@@ -264,7 +291,7 @@ class GatedLikelihood:
     stand-in with that interface)."""
 
     def __init__(self, surrogate, tau=0.05, first_train=100_000, retrain_every=0, window=100_000,
-                 margin=np.inf, train_kwargs=None):
+                 margin=np.inf, train_kwargs=None, retrain_kwargs=None):
         self.s = surrogate
         self.tau = float(tau)
         self.first_train = int(first_train)
@@ -272,6 +299,9 @@ class GatedLikelihood:
         self.window = int(window)
         self.margin = float(margin)
         self.train_kwargs = train_kwargs or {}
+        # warm retraining starts from the previous parameters and may use a
+        # smaller budget than the first training
+        self.retrain_kwargs = retrain_kwargs if retrain_kwargs is not None else self.train_kwargs
         self._th = []
         self._L = []
         self._count = 0
@@ -302,7 +332,7 @@ class GatedLikelihood:
             th, L = th[near], L[near]
         th, L = th[-self.window:], L[-self.window:]
         t0 = time.perf_counter()
-        self.s.train(th, L, **self.train_kwargs)
+        self.s.train(th, L, **(self.retrain_kwargs if self.trained else self.train_kwargs))
         self.train_seconds += time.perf_counter() - t0
         self.trained = True
         self.n_train += 1
@@ -334,7 +364,7 @@ def exact_gpu(ctx):
 
 def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0.05, first_train=100_000,
                         retrain_every=0, window=100_000, margin=np.inf, train_cfg=None, batch=512, dlogz=0.01,
-                        audit_frac=0.01, pool_factor=1, progress=0):
+                        audit_frac=0.01, pool_factor=1, progress=0, retrain_cfg=None):
     """The same nested-sampling run without and with the surrogate gate
     (same seed), and the comparison: evidence, per-bin posterior mean and
     standard deviation, exact calls avoided and wall-clock speedup."""
@@ -343,7 +373,8 @@ def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0
                           progress=progress).run()
     gate = GatedLikelihood(surrogate, tau=tau, first_train=first_train, retrain_every=retrain_every,
                            window=window, margin=margin,
-                           train_kwargs={"cfg": train_cfg} if train_cfg is not None else {})
+                           train_kwargs={"cfg": train_cfg} if train_cfg is not None else {},
+                           retrain_kwargs={"cfg": retrain_cfg} if retrain_cfg is not None else None)
     gated = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
                           gate=gate, audit_frac=audit_frac, pool_factor=pool_factor, progress=progress).run()
     m1, s1 = plain.posterior_moments()
