@@ -89,7 +89,7 @@ __device__ inline T *uniform_ptr(T *p) {
 }
 
 // Raw buffer over nbytes at p (a wave-uniform address). Loads past nbytes
-// return zero and stores past it are dropped.
+// return zero.
 __device__ inline rsrc_t make_rsrc(const void *p, int64_t nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
 }
@@ -155,7 +155,7 @@ __device__ inline void tile_update(rsrc_t A, rsrc_t P, rsrc_t Q, int K, int voff
             t3[cb][r] = ld1(A, voff + 8, so);
         }
     }
-    // The prefetch runs up to 4 (STAGES - 1) columns past K without a
+    // The prefetch runs up to 4 x (STAGES - 1) columns past K without a
     // guard: those loads fall in tile (i, j) of P's tile-row and tile (j, j)
     // of Q's, inside the slot, and are never used. A conditional load would
     // make the compiler's wait counts conservative at the merge and drain
