@@ -297,7 +297,7 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     {
         // precompute scratch: partial tiles of a row-split FP64 product, or W in reduced precision
         const size_t need = prec == EOR_PREC_FP64 ? eor::herk_scratch_bytes(m, N, c.num_cu)
-                                                  : eor::lowp_scratch_bytes(prec, m, c.n_pad);
+                                                  : eor::lowp_scratch_bytes(prec, m, c.n_pad, c.num_cu);
         if (c.lowp_bytes < need) {
             if (c.lowp) (void)hipFree(c.lowp);
             c.lowp = nullptr;

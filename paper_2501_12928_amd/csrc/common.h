@@ -129,10 +129,13 @@ inline bool valid_tuning(int stages, int wg_per_cu, int tiles) {
 }
 
 // Kernel launchers (precompute.hip, likelihood.hip).
+void herk_split(int64_t m, int64_t N, int num_cu, int &splits, int64_t &rows_per);
 size_t herk_scratch_bytes(int64_t m, int64_t N, int num_cu);
+hipError_t launch_herk_reduce(const double2 *part, int64_t tiles, int splits, int64_t n, double2 *A,
+                              hipStream_t s);
 hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ldT,
                                   const double *invvar, void *scratch, hipStream_t s);
-size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad);
+size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad, int num_cu);
 hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ldT,
                                   const double *invvar, void *scratch, hipStream_t s);
 hipError_t launch_precompute_bf16x3(const Context &c, const double2 *T, int64_t ldT,

@@ -317,12 +317,15 @@ hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ld
     double2 *out = splits > 1 ? (double2 *)scratch : c.A;
     hipLaunchKernelGGL(herk_fp64_kernel, dim3((unsigned)(tiles * splits)), dim3(256), 0, s, T, ldT, c.m, c.n,
                        invvar, tiles, rows_per, splits, out);
-    if (splits > 1) {
-        const int64_t total = tiles * TS2;
-        const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-        hipLaunchKernelGGL(herk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const double2 *)out,
-                           tiles, splits, c.n, c.A);
-    }
+    if (splits > 1) return launch_herk_reduce(out, tiles, splits, c.n, c.A, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_herk_reduce(const double2 *part, int64_t tiles, int splits, int64_t n, double2 *A,
+                              hipStream_t s) {
+    const int64_t total = tiles * TS2;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(herk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, part, tiles, splits, n, A);
     return hipGetLastError();
 }
 

@@ -86,40 +86,94 @@ __global__ void w32_kernel(const double2 *__restrict__ T, int64_t ldT, int64_t m
     }
 }
 
-__global__ __launch_bounds__(256) void herk_fp32_kernel(const float2 *__restrict__ W, int64_t m_pad,
-                                                        int64_t n_pad, int64_t n,
-                                                        double2 *__restrict__ Ap) {
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+__device__ inline rsrc_t make_rsrc(const void *p, int64_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
+}
+
+__device__ inline float2 ldf2(rsrc_t r, int voff) {
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+    float2 x;
+    __builtin_memcpy(&x, &v, sizeof(x));
+    return x;
+}
+
+// Operands of one 4-row step of W (row s0 + q in lane group q): the tile-row
+// block W[s][64 ti + 16 w + l16] and the four tile-column blocks
+// W[s][64 tj + 16 cb + l16].
+struct F32Step {
+    float2 a;
+    float2 b[4];
+};
+
+constexpr int F32_STAGES = 4;  // steps in flight; divides the 16 steps of a chunk
+
+// One work unit: tile u % tiles over rows [split * rows_per, ...), split =
+// u / tiles, rows_per a multiple of CHUNK_ROWS; W is zero-padded to m_pad
+// rows and n_pad columns, so every operand load is unguarded (the prefetch
+// past the end of W reads zero through the descriptor). With one split the
+// tile goes to A directly; otherwise to its slot of `out` (FP64), and the
+// splits are added in a fixed order afterwards.
+__global__ __launch_bounds__(256, 2) void herk_fp32_kernel(const float2 *__restrict__ W, int64_t m_pad,
+                                                           int64_t n_pad, int64_t n, int64_t tiles,
+                                                           int64_t rows_per, int splits,
+                                                           double2 *__restrict__ out) {
+    const int64_t unit = blockIdx.x;
+    const int64_t tile = unit % tiles, split = unit / tiles;
     int64_t ti, tj;
-    tile_of(blockIdx.x, ti, tj);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    tile_of(tile, ti, tj);
+    const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, q = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t r0 = split * rows_per;
+    const int64_t r1 = r0 + rows_per < m_pad ? r0 + rows_per : m_pad;
     // D[c][r] = sum_s b[s][c] conj(a[s][r]):  b = W[s][64 tj + c], a = W[s][64 ti + r]
-    const float2 *pa = W + (int64_t)q * n_pad + TS * ti + 16 * w + l16;
-    const float2 *pb = W + (int64_t)q * n_pad + TS * tj + l16;
+    const int va = (int)((q * n_pad + TS * ti + 16 * w + l16) * 8);
+    int vb[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) vb[cb] = (int)((q * n_pad + TS * tj + 16 * cb + l16) * 8);
+    auto rows_at = [&](int64_t s) {
+        const int64_t left = m_pad - s;
+        return make_rsrc(W + (left <= 0 ? 0 : s * n_pad), left <= 0 ? 0 : (left < 4 ? left : 4) * n_pad * 8);
+    };
+    auto load = [&](F32Step &st, int64_t s) {
+        const rsrc_t R = rows_at(s);
+        st.a = ldf2(R, va);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) st.b[cb] = ldf2(R, vb[cb]);
+    };
+
     double sR[4][4], sI[4][4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) sR[cb][r] = sI[cb][r] = 0.0;
 
-    for (int64_t c0 = 0; c0 < m_pad; c0 += CHUNK_ROWS) {
+    F32Step buf[F32_STAGES];
+#pragma unroll
+    for (int s0 = 0; s0 < F32_STAGES - 1; ++s0) {
+        load(buf[s0], r0 + 4 * s0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int64_t c0 = r0; c0 < r1; c0 += CHUNK_ROWS) {
+        __syncthreads();  // keep the four waves together on the shared column block
         f4 aR[4], aI[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            aR[cb] = f4{0, 0, 0, 0};
-            aI[cb] = f4{0, 0, 0, 0};
-        }
-        for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 4) {
-            const float2 a = pa[s0 * n_pad];
-            float2 b[4];
+        for (int cb = 0; cb < 4; ++cb) aR[cb] = aI[cb] = f4{0, 0, 0, 0};
+        for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 4 * F32_STAGES) {
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) b[cb] = pb[s0 * n_pad + 16 * cb];
-            const float nai = -a.y;
+            for (int u = 0; u < F32_STAGES; ++u) {
+                load(buf[(u + F32_STAGES - 1) % F32_STAGES], s0 + 4 * (u + F32_STAGES - 1));
+                const F32Step &st = buf[u];
+                const float nai = -st.a.y;
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                aR[cb] = mfma32(b[cb].x, a.x, aR[cb]);
-                aR[cb] = mfma32(b[cb].y, a.y, aR[cb]);
-                aI[cb] = mfma32(b[cb].y, a.x, aI[cb]);
-                aI[cb] = mfma32(b[cb].x, nai, aI[cb]);
+                for (int cb = 0; cb < 4; ++cb) {
+                    aR[cb] = mfma32(st.b[cb].x, st.a.x, aR[cb]);
+                    aR[cb] = mfma32(st.b[cb].y, st.a.y, aR[cb]);
+                    aI[cb] = mfma32(st.b[cb].y, st.a.x, aI[cb]);
+                    aI[cb] = mfma32(st.b[cb].x, nai, aI[cb]);
+                }
             }
         }
 #pragma unroll
@@ -130,7 +184,17 @@ __global__ __launch_bounds__(256) void herk_fp32_kernel(const float2 *__restrict
                 sI[cb][r] += (double)aI[cb][r];
             }
     }
-    store_tile(Ap, ti, tj, n, sR, sI, w, l16, q);
+    if (splits == 1) {
+        store_tile(out, ti, tj, n, sR, sI, w, l16, q);
+        return;
+    }
+    // partial tile, column-major: lane holds [16 w + l16][16 cb + 4 q + r]
+    double2 *dst = out + (split * tiles + tile) * TS2;
+    const int row = 16 * w + l16;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[(16 * cb + 4 * q + r) * TS + row] = make_double2(sR[cb][r], sI[cb][r]);
 }
 
 // -------------------------------------------------------------- BF16x3 ----
@@ -270,9 +334,21 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
 
 }  // namespace
 
-size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad) {
+// Row slices of the FP32 product: herk_split's choice, in whole chunks.
+void fp32_split(int64_t m_pad, int64_t N, int num_cu, int &splits, int64_t &rows_per) {
+    herk_split(m_pad, N, num_cu, splits, rows_per);
+    rows_per = (rows_per + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
+}
+
+size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad, int num_cu) {
     const int64_t m_pad = (m + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
-    if (prec == EOR_PREC_FP32) return (size_t)m_pad * n_pad * sizeof(float2);
+    if (prec == EOR_PREC_FP32) {
+        int splits;
+        int64_t rows_per;
+        fp32_split(m_pad, n_pad / TS, num_cu, splits, rows_per);
+        const size_t part = splits > 1 ? (size_t)splits * n_tiles(n_pad / TS) * TS2 * sizeof(double2) : 0;
+        return (size_t)m_pad * n_pad * sizeof(float2) + part;
+    }
     if (prec == EOR_PREC_BF16X3) return (size_t)6 * m_pad * n_pad * sizeof(unsigned short);
     return 0;
 }
@@ -284,8 +360,14 @@ hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ld
     const unsigned gy = (unsigned)(m_pad < 65535 ? m_pad : 65535);
     hipLaunchKernelGGL(w32_kernel, dim3((unsigned)((c.n_pad + 255) / 256), gy), dim3(256), 0, s, T, ldT,
                        c.m, c.n, invvar, m_pad, c.n_pad, W);
-    hipLaunchKernelGGL(herk_fp32_kernel, dim3((unsigned)n_tiles(c.N)), dim3(256), 0, s, W, m_pad, c.n_pad,
-                       c.n, c.A);
+    int splits;
+    int64_t rows_per;
+    fp32_split(m_pad, c.N, c.num_cu, splits, rows_per);
+    const int64_t tiles = n_tiles(c.N);
+    double2 *part = splits > 1 ? (double2 *)((char *)scratch + (size_t)m_pad * c.n_pad * sizeof(float2)) : c.A;
+    hipLaunchKernelGGL(herk_fp32_kernel, dim3((unsigned)(tiles * splits)), dim3(256), 0, s, W, m_pad, c.n_pad,
+                       c.n, tiles, rows_per, splits, part);
+    if (splits > 1) return launch_herk_reduce(part, tiles, splits, c.n, c.A, s);
     return hipGetLastError();
 }
 
