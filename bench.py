@@ -402,7 +402,13 @@ def main():
 
     fl = B * flops_per_theta(n)
     achieved = fl / (like_ms / 1e3) / 1e12
+    like_ms_median = float(np.median([a.elapsed_time(b) for a, b in events]))
     traffic = traffic_per_launch()
+    # measured FP64 matrix peak over a run about as long as one likelihood
+    # launch (a round is 8 MFMAs of 64 cycles for each of the two waves that
+    # share a SIMD: 1024 cycles)
+    probe_iters = int(like_ms * 1e-3 * 2.4e9 / 1024)
+    peak_meas, probe_ms = eor.probe_fp64_mfma(probe_iters)
     out = {
         "metric": "logL evals/s at n=4096 complex FP64, batched",
         "value": B * args.steps / wall,
@@ -423,8 +429,9 @@ def main():
                    "m": m, "n": n, "n_k": inst.n_k, "B": B},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "likelihood_kernel", "launch_ms": like_ms,
-                     "flops_per_launch": fl},
+                     "kernel": "likelihood_kernel", "launch_ms": like_ms, "launch_ms_median": like_ms_median,
+                     "flops_per_launch": fl, "peak_measured": peak_meas,
+                     "frac_measured": achieved / peak_meas, "peak_measured_run_ms": probe_ms},
         "loglike_evals_per_s": B / (like_ms / 1e3),
         "tuning": dict(zip(("stages", "wg_per_cu", "tiles_per_pass"), ctx.tuning())),
         "gated": None,

@@ -318,6 +318,18 @@ eor_status eor_surrogate_gate(eor_surrogate *s, int64_t B, const double *theta, 
 eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, const double *rows,
                             double *rows_out, int32_t *index_out, int32_t *count_out, void *stream);
 
+/*
+ * Measured FP64 matrix peak (for reporting beside the specification peak):
+ * back-to-back FP64 16x16x4 MFMAs on independent accumulators, two
+ * workgroups of four waves per CU, `iters` rounds of eight per wave, timed on
+ * a private stream after a short warm-up. A run of about the length of a
+ * likelihood launch shows the clock the part sustains under that load.
+ *   tflops  out: FP64 TFLOP/s;  ms  out (may be NULL): the timed run
+ * Synchronous; allocates and frees a small output buffer.
+ * Errors: EOR_ERR_ARG (iters outside 1..2^32, NULL tflops), EOR_ERR_HIP, EOR_ERR_OOM.
+ */
+eor_status eor_probe_fp64_mfma(int device, int64_t iters, double *tflops, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

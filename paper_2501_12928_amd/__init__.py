@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.eor_surrogate_infer.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
         L.eor_surrogate_gate.argtypes = [_P, _I64, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
         L.eor_compact_rows.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P]
+        L.eor_probe_fp64_mfma.argtypes = [ctypes.c_int, _I64, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
                      "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
                      "eor_group_set_graph", "eor_group_tuning", "eor_group_set_tuning", "eor_set_tuning",
@@ -101,7 +103,7 @@ def lib() -> ctypes.CDLL:
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
                      "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
-                     "eor_compact_rows"):
+                     "eor_compact_rows", "eor_probe_fp64_mfma"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -400,3 +402,12 @@ def compact_rows(keep, rows=None):
 
 def version() -> str:
     return lib().eor_version().decode()
+
+
+def probe_fp64_mfma(iters: int, device: int = 0):
+    """(TFLOP/s, ms) of back-to-back FP64 MFMAs on every CU for `iters`
+    rounds: the device's measured FP64 matrix peak over a run that long."""
+    t = ctypes.c_double()
+    ms = ctypes.c_double()
+    check(lib().eor_probe_fp64_mfma(device, int(iters), ctypes.byref(t), ctypes.byref(ms)))
+    return t.value, ms.value

@@ -277,3 +277,13 @@ def test_largest_shape_block_rotation():
     assert np.all(i1 == 0) and np.all(i2 == 0) and np.all(ib == 0)
     ref = l1 + l2
     assert np.all(np.abs(lb - ref) <= tol(ref)), np.max(np.abs(lb - ref))
+
+
+def test_fp64_mfma_probe():
+    """The measured FP64 matrix peak is positive and below the part's
+    specification (78.6 TFLOP/s at 2.4 GHz); bad arguments are refused."""
+    import paper_2501_12928_amd as eor
+    tf, ms = eor.probe_fp64_mfma(20000)
+    assert 10.0 < tf <= 80.0 and ms > 0.0, (tf, ms)
+    with pytest.raises(eor.EorError):
+        eor.probe_fp64_mfma(0)
