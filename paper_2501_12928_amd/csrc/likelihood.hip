@@ -24,8 +24,8 @@
 // first round group 1 updates tile j + 1 while group 0 forms the diagonal,
 // and holds its accumulators until L_jj^{-1} is ready.
 //
-// The panel updates form each complex product from three real FP64 MFMAs
-// (Gauss's trick) instead of four; the TRSM step keeps four. A tile's
+// The panel updates and the TRSM form each complex product from three real
+// FP64 MFMAs (Gauss's trick) instead of four. A tile's
 // accumulators start from A_ij (loaded while the panel prefetch is in
 // flight), so the update ends with X itself.
 //
@@ -433,7 +433,10 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                     double wr[4] = {0, 0, 0, 0}, wi[4] = {0, 0, 0, 0};
 #pragma unroll
                     for (int cb2 = 0; cb2 < 4; ++cb2) {
-                        d4 yR = d4{0, 0, 0, 0}, yI = d4{0, 0, 0, 0};
+                        // x conj(l) with three real products (Gauss):
+                        //   T1 = xr lr, T2 = xi li, T3 = (xr + xi)(lr - li)
+                        //   re = T1 + T2, im = xi lr - xr li = T3 - T1 + T2
+                        d4 t1 = d4{0, 0, 0, 0}, t2 = d4{0, 0, 0, 0}, t3 = d4{0, 0, 0, 0};
 #pragma unroll
                         for (int cb = 0; cb <= cb2; ++cb) {
 #pragma unroll
@@ -441,12 +444,12 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                                 // Linv[16cb2 + l16][16cb + 4r + q]
                                 const double2 lv = Dt[lt + (16 * cb + 4 * r) * TS + 16 * cb2];
                                 const double ar = xr[cb][r], ai = xi[cb][r];
-                                yR = mfma64(ar, lv.x, yR);
-                                yR = mfma64(ai, lv.y, yR);
-                                yI = mfma64(ai, lv.x, yI);
-                                yI = mfma64(-ar, lv.y, yI);
+                                t1 = mfma64(ar, lv.x, t1);
+                                t2 = mfma64(ai, lv.y, t2);
+                                t3 = mfma64(ar + ai, lv.x - lv.y, t3);
                             }
                         }
+                        const d4 yR = t1 + t2, yI = t3 - t1 + t2;
                         // lane holds Y[16w + q + 4r][16cb2 + l16]
                         const double2 yc = ys[16 * cb2 + l16];
 #pragma unroll
