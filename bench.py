@@ -307,7 +307,8 @@ def bench_gated(args):
         "plain_proposals_per_s": plain.n_proposed / plain.wall_s,
         "comparison": cmp,
         "posterior_mean": m.tolist(), "posterior_std": sd.tolist(),
-        "theta_true": inst.theta_true.tolist()}))
+        "theta_true": inst.theta_true.tolist(),
+        "power_recovery": gated.power_summary(inst.theta_true)}))
     sur.close()
     ctx.close()
 

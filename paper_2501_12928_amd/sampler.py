@@ -65,6 +65,35 @@ class Result:
         var = w @ (self.samples - mean) ** 2
         return mean, np.sqrt(var)
 
+    def power_summary(self, theta_true=None):
+        """Per k-bin power P_b = 10^theta_b recovered from the weighted
+        samples (theta is log10 power per bin): posterior mean and standard
+        deviation of P_b, the median and 16-84% interval of theta_b, and, given
+        the values the data were drawn at, the fractional error of the mean
+        power and the offset of the median in posterior standard deviations."""
+        w = np.exp(self.logw - self.logw.max())
+        w /= w.sum()
+        P = 10.0 ** self.samples
+        pm = w @ P
+        ps = np.sqrt(w @ (P - pm) ** 2)
+        out = {"power_mean": pm.tolist(), "power_std": ps.tolist(),
+               "theta_median": [], "theta_lo": [], "theta_hi": []}
+        for b in range(self.samples.shape[1]):
+            order = np.argsort(self.samples[:, b])
+            cw = np.cumsum(w[order])
+            q = lambda f: float(self.samples[order[min(np.searchsorted(cw, f), len(cw) - 1)], b])
+            out["theta_median"].append(q(0.5))
+            out["theta_lo"].append(q(0.16))
+            out["theta_hi"].append(q(0.84))
+        if theta_true is not None:
+            tt = np.asarray(theta_true, dtype=np.float64)
+            pt = 10.0 ** tt
+            out["power_true"] = pt.tolist()
+            out["power_frac_err"] = ((pm - pt) / pt).tolist()
+            half = 0.5 * (np.array(out["theta_hi"]) - np.array(out["theta_lo"]))
+            out["theta_offset_sigma"] = ((np.array(out["theta_median"]) - tt) / half).tolist()
+        return out
+
 
 def _logsubexp(a, b):
     """log(exp(a) - exp(b)) for a > b."""

@@ -59,6 +59,14 @@ def test_gaussian_evidence_and_posterior():
     # information of a Gaussian in a wide box: H = ln(V / (2 pi e sigma^2)^(d/2)) approx.
     H_true = d * math.log(HI - LO) - 0.5 * d * math.log(2 * math.pi * math.e * SIG ** 2)
     assert abs(r.information - H_true) < 0.3
+    # power recovery: theta ~ N(mu, sigma^2) gives E[10^theta] = 10^mu exp((sigma ln 10)^2 / 2),
+    # median mu and 16-84% interval mu +- sigma
+    ps = r.power_summary(theta_true=MU[:d])
+    expect = 10.0 ** MU[:d] * math.exp((SIG * math.log(10.0)) ** 2 / 2)
+    np.testing.assert_allclose(ps["power_mean"], expect, rtol=0.12)
+    np.testing.assert_allclose(ps["theta_median"], MU[:d], atol=0.06)
+    np.testing.assert_allclose(np.array(ps["theta_hi"]) - np.array(ps["theta_lo"]), 2 * SIG, rtol=0.12)
+    assert np.all(np.abs(ps["theta_offset_sigma"]) < 0.15)
 
 
 def test_gated_perfect_surrogate_keeps_answer_with_fewer_exact_calls():
