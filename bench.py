@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix)
 CONFIG_ID = 3               # 20000 x 4096, 12 bins, B = 512
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_12928_amd", "csrc", "likelihood.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "likelihood_n4096_B512_traffic.json")
@@ -313,6 +314,96 @@ def bench_gated(args):
     ctx.close()
 
 
+def surrogate_flops(n_in: int, H: int):
+    """(inference, training) FP32 flop per sample and member of an
+    n_in -> H -> H -> 1 network: the forward pass is its three dense layers;
+    a training step adds the weight gradients of both hidden layers and the
+    input gradient of the second (two multiply-adds per weight each)."""
+    fwd = 2.0 * (n_in * H + H * H + H)
+    bwd = 2.0 * (n_in * H + H * H) + 2.0 * H * H + 2.0 * H
+    return fwd, fwd + bwd
+
+
+def bench_surrogate(args):
+    """Throughput of the learned part alone: training the 5-member ensemble
+    (12 -> 256 -> 256 -> 1, GELU, FP32) on 1e5 exact evaluations, then gating
+    1e6 prior proposals. The training targets are exact FP64 logL values of a
+    12-bin instance at n = 1024 (cheap to evaluate; the network only sees them
+    standardised)."""
+    import torch
+    import synth
+    import paper_2501_12928_amd as eor
+    n_train, n_prop = args.surrogate_train, args.surrogate_proposals
+    inst = synth.small(3001, m=4096, n=1024, n_k=12, n_theta=1)
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale)
+    rng = np.random.default_rng(3002)
+    theta = torch.from_numpy(synth.theta_batch(rng, n_train, inst.n_k, inst.lo, inst.hi)).cuda()
+    logL = torch.empty(n_train, dtype=torch.float64, device="cuda")
+    info = torch.empty(n_train, dtype=torch.int32, device="cuda")
+    for c0 in range(0, n_train, 4096):
+        c1 = min(n_train, c0 + 4096)
+        ctx.loglike_batch(theta[c0:c1], out=logL[c0:c1], info=info[c0:c1])
+    torch.cuda.synchronize()
+    ctx.close()
+    if not bool((info == 0).all().item()):
+        print(json.dumps({"error": "failed exact evaluations in the training set"}))
+        sys.exit(1)
+    H, M = 256, 5
+    sur = eor.Surrogate(inst.n_k, inst.lo, inst.hi, n_members=M, hidden=H, seed=1)
+    # early stopping off: a fixed number of epochs is timed
+    cfg = eor.train_cfg(epochs=args.surrogate_epochs, minibatch=args.train_minibatch,
+                        patience=args.surrogate_epochs + 1, lr=1e-3, seed=5)
+    warm = eor.train_cfg(epochs=2, minibatch=args.train_minibatch, patience=3, lr=1e-3, seed=4)
+    sur.train(theta, logL, warm)          # builds the epoch graph and the buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    epochs, val = sur.train(theta, logL, cfg)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    n_val = max(1, int(0.1 * n_train))
+    n_tr = n_train - n_val
+    steps = max(1, n_tr // min(args.train_minibatch, n_tr))
+    samples_per_epoch = steps * min(args.train_minibatch, n_tr)
+    f_inf, f_train = surrogate_flops(inst.n_k, H)
+    train_flop = epochs * M * (samples_per_epoch * f_train + n_val * f_inf)
+
+    prop = torch.from_numpy(synth.theta_batch(rng, n_prop, inst.n_k, inst.lo, inst.hi)).cuda()
+    L_min = float(torch.quantile(logL, 0.5).item())
+    stream = torch.cuda.current_stream()
+    sur.gate(prop, L_min, args.tau)
+    torch.cuda.synchronize()
+    reps = 5
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        mean, spread, dec = sur.gate(prop, L_min, args.tau)
+        b.record(stream)
+    torch.cuda.synchronize()
+    gate_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    gate_flop = n_prop * M * f_inf
+    achieved = gate_flop / (gate_ms / 1e3) / 1e12
+    sur.close()
+    print(json.dumps({
+        "metric": "surrogate proposals gated per second (5 x MLP 12-256-256-1, FP32)",
+        "value": n_prop / (gate_ms / 1e3), "unit": "proposals/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"train on {n_train} exact logL of a 12-bin n=1024 instance "
+                               f"({args.surrogate_epochs} epochs, minibatch {args.train_minibatch}, "
+                               f"10% validation); gate {n_prop} prior proposals at tau={args.tau}",
+                   "members": M, "hidden": H, "n_in": inst.n_k},
+        "gate_ms": gate_ms, "gate_tflops": achieved,
+        "gate_rejected_frac": float((dec == 0).float().mean().item()),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "surrogate gate (all kernels)",
+                     "flops_per_launch": gate_flop},
+        "train": {"seconds": train_s, "epochs": epochs, "samples_per_epoch": samples_per_epoch,
+                  "sample_epochs_per_s": epochs * samples_per_epoch * M / train_s,
+                  "tflops": train_flop / train_s / 1e12, "val_loss": val.tolist()},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,10 +411,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
-    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress", "surrogate"], default="metric",
                     help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances; "
                          "gated: nested sampling at 20000x4096 without and with the surrogate gate; "
-                         "stress: reduced precision on ill-conditioned instruments at 8000x2048")
+                         "stress: reduced precision on ill-conditioned instruments at 8000x2048; "
+                         "surrogate: ensemble training on 1e5 samples and gating of 1e6 proposals")
     ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
     ap.add_argument("--n-live", type=int, default=500)
     ap.add_argument("--first-train", type=int, default=30000)
@@ -336,6 +428,9 @@ def main():
                     help="epochs of each warm retraining (default: as the first training)")
     ap.add_argument("--train-minibatch", type=int, default=512)
     ap.add_argument("--pool-factor", type=int, default=1)
+    ap.add_argument("--surrogate-train", type=int, default=100000)
+    ap.add_argument("--surrogate-proposals", type=int, default=1000000)
+    ap.add_argument("--surrogate-epochs", type=int, default=50)
     ap.add_argument("--tuning", default=None,
                     help="launch choices 'stages,wg_per_cu,tiles_per_pass' of the likelihood batch "
                          "(default: the library's)")
@@ -369,6 +464,8 @@ def main():
         return bench_gated(args)
     if args.workload == "stress":
         return bench_stress(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
 
     inst = synth.gen(CONFIG_ID)
     B, n, m = inst.theta.shape[0], inst.n, inst.m
