@@ -241,8 +241,9 @@ typedef struct {
 /*
  * Create an ensemble on HIP device `device` with He-normal weights (one
  * seeded stream per member) and zero biases. lo, hi: host double [n_in],
- * hi > lo, the prior box. Sizes: 1 <= n_in <= 1024, 1 <= n_members <= 64,
- * 1 <= hidden <= 4096.
+ * hi > lo, the prior box. Sizes: 1 <= n_in <= 64, 1 <= n_members <= 64,
+ * hidden a multiple of 4 in [4, 512] (one workgroup keeps a block of samples'
+ * activations of both hidden layers in LDS). Anything else: EOR_ERR_ARG.
  */
 eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int32_t hidden,
                                 uint64_t seed, const double *lo, const double *hi,

@@ -6,15 +6,25 @@
 //
 // Layout per member (flat FP32, row-major matrices):
 //   W1 [H x n_in], b1 [H], W2 [H x H], b2 [H], W3 [H], b3 [1]
-// Members are stored one after another (stride P = number of parameters).
+// (P numbers). On the device member z starts at z * PP, PP = P rounded up
+// to 64 floats, so that with H % 4 == 0 every row of W2 is 16-byte aligned;
+// the API copies in and out of the packed [members x P] layout.
 // Inputs are theta mapped from the prior box to [-1, 1]; targets are logL
 // standardised by the training mean and standard deviation.
 //
-// The dense layers and the weight gradients are one batched GEMM kernel on
-// FP32 MFMA (16x16x4): a 64 x 64 output tile per workgroup, operand tiles of
-// 16 k staged in LDS with coalesced loads whatever the operand strides.
-// Every reduction (loss, biases, output layer) has a fixed order, so
-// training is deterministic for a given seed.
+// One training step is two kernels:
+//  - mlp_kernel<NT, 1, true>: one workgroup per 16 samples of one member
+//    gathers its inputs, runs both hidden layers, the output, the loss and
+//    the backward pass down to dZ1 with the activations in LDS and
+//    registers (FP32 MFMA 16x16x4), writes H1^T and dZ2^T (the operands of
+//    the W2 gradient) and its samples' share of every other gradient;
+//  - mlp_update_kernel: the W2 gradient as a sum over the minibatch on MFMA
+//    (32 x 32 tile per workgroup) and the fixed-order sum of the per-block
+//    shares of the other parameters, each followed by the Adam update of the
+//    same parameters.
+// Inference is mlp_kernel without the backward pass, 32 samples per
+// workgroup. Every reduction has a fixed order, so training is
+// deterministic for a given seed.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -30,6 +40,11 @@ namespace {
 
 using eor::f4;
 
+constexpr int NI_MAX = 64;       // network inputs
+constexpr int XS = NI_MAX + 4;   // LDS row stride of the inputs
+constexpr int H_MAX = 512;       // hidden units (a multiple of 4)
+constexpr int ST = 16;           // samples per MFMA row tile
+
 __device__ inline f4 mfma32(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -40,82 +55,439 @@ __device__ inline float gelu_grad_f(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
-// C[z][i][j] = sum_k A[z][i][k] B[z][k][j]  (+ bias[z][j]) (GELU), with
-// A[z][i][k] at A + z sAz + i sai + k sak and B[z][k][j] at B + z sBz + k sbk + j sbj.
-struct GemmArgs {
-    const float *A;
-    int64_t sai, sak, sAz;
-    const float *B;
-    int64_t sbk, sbj, sBz;
-    float *C;
-    int64_t ldc, sCz;
-    float *Z;              // pre-activation output (epilogue 2), same layout as C
-    const float *bias;     // [z][j]
-    int64_t sbiasz;
-    int M, N, K;
-    int epi;               // 0: AB; 1: AB + bias; 2: Z = AB + bias, C = GELU(Z)
+// Adam with bias-corrected moments, c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__device__ inline void adam_update(float *p, float g, float *m, float *v, float lr, float b1, float b2, float eps,
+                                   float c1, float c2) {
+    const float me = b1 * *m + (1.0f - b1) * g;
+    const float ve = b2 * *v + (1.0f - b2) * g * g;
+    *m = me;
+    *v = ve;
+    *p -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
+}
+
+__device__ inline void adam_factors(const int64_t *step, int64_t add, float b1, float b2, float *c1, float *c2) {
+    const double t = (double)(*step + add + 1);
+    *c1 = (float)(1.0 - pow((double)b1, t));
+    *c2 = (float)(1.0 - pow((double)b2, t));
+}
+
+struct MlpArgs {
+    // input row of sample s of member z: r = idx ? idx[z idxz + s] : s; its
+    // features are theta[r] mapped to [-1, 1] (when theta is set, shared by
+    // all members) or X[z xz + r n_in ...]; its target Y[z yz + r]
+    const float *X;
+    int64_t xz;
+    const double *theta, *lo, *hi;
+    const int32_t *idx;
+    int64_t idxz;
+    const float *Y;
+    int64_t yz;
+    int nb;  // samples (the loss is their mean)
+    const float *params;
+    int64_t PP, offb1, offW2, offb2, offW3, offb3;
+    int n_in, H;
+    // forward only: f[z fz + s] = network output, minus the target when Y is set
+    float *f;
+    int64_t fz;
+    // backward: H1T, dZ2T [z][64 NT][nbp]; part [z][block][PS]
+    float *H1T, *dZ2T;
+    int64_t nbp;
+    float *part;
+    int64_t PS;
 };
 
-constexpr int GT = 64;  // output tile
-constexpr int GK = 16;  // k per LDS stage
+// Shares of one block of samples, in part[z][block][...]: gW1 [H x n_in],
+// gb1 [H], gb2 [H], gW3 [H], gb3, and the block's sum of squared residuals.
+__host__ __device__ inline int64_t share_count(int H, int n_in) { return (int64_t)H * n_in + 3 * (int64_t)H + 2; }
 
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-    __shared__ float As[GK][GT];
-    __shared__ float Bs[GK][GT];
+// One workgroup of four waves per RT * 16 samples of member blockIdx.y;
+// wave w owns hidden units [16 NT w, 16 NT (w + 1)) of both layers (the
+// hidden width is padded to 64 NT; padded units carry zero weights and stay
+// exactly zero). In an MFMA step t, lane group q = lane / 16 supplies the
+// operand pair of reduction index 4 q + t within a group of 16, for A and
+// B alike, so that each lane loads four consecutive k with one 16-byte read.
+template <int NT, int RT, bool BWD>
+__global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
+    static_assert(!BWD || RT == 1, "the backward pass takes 16 samples per workgroup");
+    constexpr int FS = ST * RT;       // samples per workgroup
+    constexpr int HP = 64 * NT;
+    constexpr int HS = HP + 4;        // LDS row stride of the hidden activations
+    __shared__ __align__(16) float xs[FS * XS];
+    __shared__ __align__(16) float hs[FS * HS];
+    __shared__ float fpart[4 * FS];
+    __shared__ float dfs[FS];
+    __shared__ float r2s[FS];
+    const int z = blockIdx.y, s0 = blockIdx.x * FS;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-    const int64_t z = blockIdx.z;
-    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
-    const float *A = g.A + z * g.sAz;
-    const float *B = g.B + z * g.sBz;
-    f4 acc[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = f4{0, 0, 0, 0};
-    const bool a_kcontig = g.sak == 1;
-    const bool b_jcontig = g.sbj == 1;
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
-        // stage the operand tiles; consecutive threads walk the unit-stride dimension
-        for (int e = tid; e < GK * GT; e += 256) {
-            int i, kk;
-            if (a_kcontig) { i = e / GK; kk = e % GK; } else { i = e % GT; kk = e / GT; }
-            const int gi = i0 + i, gk = k0 + kk;
-            As[kk][i] = (gi < g.M && gk < g.K) ? A[gi * g.sai + gk * g.sak] : 0.0f;
-            int j, kb;
-            if (b_jcontig) { j = e % GT; kb = e / GT; } else { j = e / GK; kb = e % GK; }
-            const int gj = j0 + j, gkb = k0 + kb;
-            Bs[kb][j] = (gj < g.N && gkb < g.K) ? B[gkb * g.sbk + gj * g.sbj] : 0.0f;
+    const int H = a.H, n_in = a.n_in, nip = (n_in + 15) & ~15, HK = (H + 15) & ~15;
+    const float *P = a.params + (int64_t)z * a.PP;
+    const float *W2 = P + a.offW2;
+
+    for (int e = tid; e < FS * nip; e += 256) {
+        const int s = e / nip, k = e - s * nip, gs = s0 + s;
+        float v = 0.0f;
+        if (k < n_in && gs < a.nb) {
+            const int64_t r = a.idx ? (int64_t)a.idx[z * a.idxz + gs] : (int64_t)gs;
+            if (a.theta)
+                v = (float)(2.0 * (a.theta[r * n_in + k] - a.lo[k]) / (a.hi[k] - a.lo[k]) - 1.0);
+            else
+                v = a.X[z * a.xz + r * n_in + k];
         }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < GK; ks += 4) {
-            const float a = As[ks + q][16 * w + l16];
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma32(a, Bs[ks + q][16 * cb + l16], acc[cb]);
-        }
-        __syncthreads();
+        xs[s * XS + k] = v;
     }
-    // lane holds D[16w + 4q + r][16cb + l16]
-    float *C = g.C + z * g.sCz;
-    float *Zp = g.Z ? g.Z + z * g.sCz : nullptr;
-    const float *bias = g.bias ? g.bias + z * g.sbiasz : nullptr;
+    __syncthreads();
+
+    const int hb = 16 * NT * w;
+    f4 acc[RT][NT];
+    // layer 1: Z1[s][h] = sum_k x[s][k] W1[h][k] + b1[h]
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        const int j = j0 + 16 * cb + l16;
-        if (j >= g.N) continue;
-        const float bj = (g.epi >= 1) ? bias[j] : 0.0f;
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[rt][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int g = 0; g < nip; g += 16) {
+        float wv[NT][4];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int h = hb + 16 * c + l16;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = g + 4 * q + t;
+                wv[c][t] = (h < H && k < n_in) ? P[h * n_in + k] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const f4 xv = *reinterpret_cast<const f4 *>(&xs[(ST * rt + l16) * XS + g + 4 * q]);
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[rt][c] = mfma32(xv[t], wv[c][t], acc[rt][c]);
+        }
+    }
+    // lane holds Z1[16 rt + 4 q + r][hb + 16 c + l16]
+    f4 g1[BWD ? NT : 1];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const int h = hb + 16 * c + l16;
+        const float b = h < H ? P[a.offb1 + h] : 0.0f;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            f4 hv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float zz = acc[rt][c][r] + b;
+                hv[r] = gelu_f(zz);
+                if constexpr (BWD) g1[c][r] = gelu_grad_f(zz);
+                hs[(ST * rt + 4 * q + r) * HS + h] = hv[r];
+            }
+            if constexpr (BWD) *reinterpret_cast<f4 *>(&a.H1T[((int64_t)z * HP + h) * a.nbp + s0 + 4 * q]) = hv;
+        }
+    }
+    __syncthreads();
+
+    // layer 2: Z2[s][o] = sum_k H1[s][k] W2[o][k] + b2[o]
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[rt][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    // W2 reads run one group of 16 k ahead of the MFMAs that use them
+    f4 wv[NT];
+    auto load_w2 = [&](int g, f4 *dst) {
+        const bool kin = g + 4 * q < H;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int o = hb + 16 * c + l16;
+            dst[c] = (o < H && kin) ? *reinterpret_cast<const f4 *>(&W2[(int64_t)o * H + g + 4 * q])
+                                    : f4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    load_w2(0, wv);
+    for (int g = 0; g < HK; g += 16) {
+        f4 wn[NT];
+        load_w2(g + 16, wn);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const f4 hv = *reinterpret_cast<const f4 *>(&hs[(ST * rt + l16) * HS + g + 4 * q]);
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[rt][c] = mfma32(hv[t], wv[c][t], acc[rt][c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NT; ++c) wv[c] = wn[c];
+    }
+    // output f[s] = sum_o GELU(Z2[s][o]) W3[o] + b3: this wave's units, then
+    // the 16 lanes of a group (fixed xor tree), then the four waves in order
+    f4 h2[BWD ? NT : 1], gw[BWD ? NT : 1];
+    float fp[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fp[rt][r] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const int o = hb + 16 * c + l16;
+        const float b = o < H ? P[a.offb2 + o] : 0.0f;
+        const float w3 = o < H ? P[a.offW3 + o] : 0.0f;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float zz = acc[rt][c][r] + b;
+                const float hv = gelu_f(zz);
+                fp[rt][r] += hv * w3;
+                if constexpr (BWD) {
+                    h2[c][r] = hv;
+                    gw[c][r] = w3 * gelu_grad_f(zz);
+                }
+            }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = i0 + 16 * w + 4 * q + r;
-            if (i >= g.M) continue;
-            const float v = acc[cb][r] + bj;
-            if (g.epi == 2) {
-                Zp[(int64_t)i * g.ldc + j] = v;
-                C[(int64_t)i * g.ldc + j] = gelu_f(v);
-            } else {
-                C[(int64_t)i * g.ldc + j] = v;
+            float v = fp[rt][r];
+            v += __shfl_xor(v, 8);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 1);
+            if (l16 == 0) fpart[w * FS + ST * rt + 4 * q + r] = v;
+        }
+    __syncthreads();
+    if (tid < FS) {
+        const int s = tid, gs = s0 + s;
+        float f = fpart[s];
+        f += fpart[FS + s];
+        f += fpart[2 * FS + s];
+        f += fpart[3 * FS + s];
+        f += P[a.offb3];
+        const bool valid = gs < a.nb;
+        float res = 0.0f;
+        if (valid && a.Y) {
+            const int64_t r = a.idx ? (int64_t)a.idx[z * a.idxz + gs] : (int64_t)gs;
+            res = f - a.Y[z * a.yz + r];
+        }
+        if constexpr (BWD) {
+            dfs[s] = valid ? 2.0f * res / (float)a.nb : 0.0f;
+            r2s[s] = res * res;
+        } else {
+            if (valid) a.f[z * a.fz + gs] = a.Y ? res : f;
+        }
+    }
+    if constexpr (BWD) {
+        float *part = a.part + ((int64_t)z * gridDim.x + blockIdx.x) * a.PS;
+        const int64_t pW1 = 0, pb1 = (int64_t)H * n_in, pb2 = pb1 + H, pW3 = pb2 + H, pb3 = pW3 + H;
+        __syncthreads();
+        // dZ2 = dF W3 GELU'(Z2): into LDS (the A operand of dH1) and dZ2^T
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int o = hb + 16 * c + l16;
+            f4 d;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                d[r] = dfs[4 * q + r] * gw[c][r];
+                hs[(4 * q + r) * HS + o] = d[r];
+            }
+            *reinterpret_cast<f4 *>(&a.dZ2T[((int64_t)z * HP + o) * a.nbp + s0 + 4 * q]) = d;
+            float sb = ((d[0] + d[1]) + d[2]) + d[3];
+            float sw = dfs[4 * q] * h2[c][0];
+            sw += dfs[4 * q + 1] * h2[c][1];
+            sw += dfs[4 * q + 2] * h2[c][2];
+            sw += dfs[4 * q + 3] * h2[c][3];
+            sb += __shfl_xor(sb, 16);
+            sb += __shfl_xor(sb, 32);
+            sw += __shfl_xor(sw, 16);
+            sw += __shfl_xor(sw, 32);
+            if (q == 0 && o < H) {
+                part[pb2 + o] = sb;
+                part[pW3 + o] = sw;
+            }
+        }
+        if (tid == 0) {
+            float sb = 0.0f, sl = 0.0f;
+            for (int s = 0; s < ST; ++s) {
+                sb += dfs[s];
+                sl += r2s[s];
+            }
+            part[pb3] = sb;
+            part[pb3 + 1] = sl;
+        }
+        __syncthreads();
+        // dH1[s][i] = sum_o dZ2[s][o] W2[o][i]
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[0][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        float wt[4][NT];
+        auto load_w2t = [&](int g, float (*dst)[NT]) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int o = g + 4 * q + t;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const int i = hb + 16 * c + l16;
+                    dst[t][c] = (o < H && i < H) ? W2[(int64_t)o * H + i] : 0.0f;
+                }
+            }
+        };
+        load_w2t(0, wt);
+        for (int g = 0; g < HK; g += 16) {
+            float wn[4][NT];
+            load_w2t(g + 16, wn);
+            const f4 dv = *reinterpret_cast<const f4 *>(&hs[l16 * HS + g + 4 * q]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[0][c] = mfma32(dv[t], wt[t][c], acc[0][c]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) wt[t][c] = wn[t][c];
+        }
+        // dZ1 = dH1 GELU'(Z1); shares of gb1 and of gW1 = dZ1^T x (the lane's
+        // dZ1 values are the A operand of that product as they stand)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int h = hb + 16 * c + l16;
+            f4 d1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d1[r] = acc[0][c][r] * g1[c][r];
+            float sb = ((d1[0] + d1[1]) + d1[2]) + d1[3];
+            sb += __shfl_xor(sb, 16);
+            sb += __shfl_xor(sb, 32);
+            if (q == 0 && h < H) part[pb1 + h] = sb;
+            for (int g = 0; g < nip; g += 16) {
+                f4 ga = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) ga = mfma32(d1[t], xs[(4 * q + t) * XS + g + l16], ga);
+                // lane holds gW1[hb + 16 c + 4 q + r][g + l16]
+                const int k = g + l16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int hh = hb + 16 * c + 4 * q + r;
+                    if (hh < H && k < n_in) part[pW1 + (int64_t)hh * n_in + k] = ga[r];
+                }
             }
         }
     }
 }
+
+struct UpdArgs {
+    const float *H1T, *dZ2T;  // [z][HP][nbp]
+    int64_t nbp;
+    int HP;
+    const float *part;        // [z][nblk][PS]
+    int64_t PS;
+    int nblk;
+    int H, n_in, nb;
+    int64_t PP, offb1, offW2, offb2, offW3, offb3;
+    float *grad;              // [z][PP], written when set
+    float *loss;              // [z], written when set
+    float *params, *mom, *vel;  // Adam when params is set
+    float lr, b1, b2, eps;
+    const int64_t *step;      // Adam step t = *step + step_add + 1
+    int64_t step_add;
+};
+
+// Workgroups [0, (HP/32)^2) of member blockIdx.y: a 32 x 32 tile of
+// gW2[o][i] = sum_s dZ2[s][o] H1[s][i] (one 16 x 16 MFMA tile per wave,
+// reduction over the padded batch, whose padding holds dZ2 = 0); the
+// others: 256 consecutive shares each, summed over the blocks in order.
+__global__ __launch_bounds__(256) void mlp_update_kernel(UpdArgs a) {
+    const int z = blockIdx.y, tid = threadIdx.x;
+    const int tt = a.HP / 32, ntile = tt * tt;
+    const int64_t zp = (int64_t)z * a.PP;
+    float c1 = 1.0f, c2 = 1.0f;
+    if (a.params) adam_factors(a.step, a.step_add, a.b1, a.b2, &c1, &c2);
+    if ((int)blockIdx.x < ntile) {
+        const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+        const int o0 = 32 * ((int)blockIdx.x / tt) + 16 * (w & 1);
+        const int i0 = 32 * ((int)blockIdx.x % tt) + 16 * (w >> 1);
+        const float *Ar = a.dZ2T + ((int64_t)z * a.HP + o0 + l16) * a.nbp + 4 * q;
+        const float *Br = a.H1T + ((int64_t)z * a.HP + i0 + l16) * a.nbp + 4 * q;
+        f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        int64_t k0 = 0;
+        for (; k0 + 64 <= a.nbp; k0 += 64) {
+            f4 av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                av[u] = *reinterpret_cast<const f4 *>(Ar + k0 + 16 * u);
+                bv[u] = *reinterpret_cast<const f4 *>(Br + k0 + 16 * u);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc = mfma32(av[u][t], bv[u][t], acc);
+        }
+        for (; k0 < a.nbp; k0 += 16) {
+            const f4 av = *reinterpret_cast<const f4 *>(Ar + k0);
+            const f4 bv = *reinterpret_cast<const f4 *>(Br + k0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = mfma32(av[t], bv[t], acc);
+        }
+        const int i = i0 + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = o0 + 4 * q + r;
+            if (o < a.H && i < a.H) {
+                const int64_t e = zp + a.offW2 + (int64_t)o * a.H + i;
+                if (a.grad) a.grad[e] = acc[r];
+                if (a.params) adam_update(&a.params[e], acc[r], &a.mom[e], &a.vel[e], a.lr, a.b1, a.b2, a.eps, c1, c2);
+            }
+        }
+        return;
+    }
+    const int64_t e = (int64_t)((int)blockIdx.x - ntile) * 256 + tid;
+    const int64_t ns = a.PS - 1;  // the last share is the squared residuals
+    if (e > ns) return;
+    const float *pp = a.part + (int64_t)z * a.nblk * a.PS + e;
+    float g = 0.0f;
+    for (int b = 0; b < a.nblk; ++b) g += pp[(int64_t)b * a.PS];
+    if (e == ns) {
+        if (a.loss) a.loss[z] = g / (float)a.nb;
+        return;
+    }
+    const int64_t HW1 = (int64_t)a.H * a.n_in;
+    int64_t off;
+    if (e < HW1) off = e;
+    else if (e < HW1 + a.H) off = a.offb1 + (e - HW1);
+    else if (e < HW1 + 2 * a.H) off = a.offb2 + (e - HW1 - a.H);
+    else if (e < HW1 + 3 * a.H) off = a.offW3 + (e - HW1 - 2 * a.H);
+    else off = a.offb3;
+    const int64_t pe = zp + off;
+    if (a.grad) a.grad[pe] = g;
+    if (a.params) adam_update(&a.params[pe], g, &a.mom[pe], &a.vel[pe], a.lr, a.b1, a.b2, a.eps, c1, c2);
+}
+
+// loss[z] = mean over s < n of r[z][s]^2 (one workgroup per member, fixed order).
+__global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ r, int n, float *__restrict__ loss) {
+    __shared__ float red[256];
+    const int z = blockIdx.x;
+    float acc = 0.0f;
+    for (int s = threadIdx.x; s < n; s += 256) {
+        const float v = r[(int64_t)z * n + s];
+        acc += v * v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[z] = red[0] / (float)n;
+}
+
+// Adam on all n parameters from the stored gradient; the step count lives in
+// device memory.
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            const int64_t *__restrict__ step) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float c1, c2;
+    adam_factors(step, 0, b1, b2, &c1, &c2);
+    adam_update(&p[e], g[e], &m[e], &v[e], lr, b1, b2, eps, c1, c2);
+}
+
+__global__ void tick_kernel(int64_t *step, int64_t add) { *step += add; }
 
 // x = 2 (theta - lo) / (hi - lo) - 1 (FP32) and, if logL is given,
 // y = (logL - mean) / std (FP32).
@@ -129,118 +501,6 @@ __global__ void scale_kernel(const double *__restrict__ theta, const double *__r
     }
     if (logL && e < N) Y[e] = (float)((logL[e] - ymean) / ystd);
 }
-
-// Xb[z][s][:] = X[idx[z][s]][:], Yb[z][s] = Y[idx[z][s]] for s < nb.
-__global__ void gather_kernel(const float *__restrict__ X, const float *__restrict__ Y, int n_in,
-                              const int32_t *__restrict__ idx, int64_t idx_stride, int nb,
-                              float *__restrict__ Xb, float *__restrict__ Yb) {
-    const int z = blockIdx.y;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nb * n_in) return;
-    const int s = e / n_in, k = e % n_in;
-    const int32_t src = idx[z * idx_stride + s];
-    Xb[((int64_t)z * nb + s) * n_in + k] = X[(int64_t)src * n_in + k];
-    if (k == 0) Yb[(int64_t)z * nb + s] = Y[src];
-}
-
-// f[z][s] = sum_k H2[z][s][k] W3[z][k] + b3[z]: one wave per (z, s), lanes
-// over k, fixed shuffle tree.
-__global__ void out_fwd_kernel(const float *__restrict__ H2, int64_t sHz, int H, const float *__restrict__ params,
-                               int64_t P, int64_t offW3, int nb, float *__restrict__ f) {
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    const int z = blockIdx.y;
-    if (wave >= nb) return;
-    const float *h = H2 + z * sHz + (int64_t)wave * H;
-    const float *W3 = params + z * P + offW3;
-    float s = 0.0f;
-    for (int k = lane; k < H; k += 64) s += h[k] * W3[k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) f[(int64_t)z * nb + wave] = s + W3[H];  // b3 follows W3
-}
-
-// Per member: r = f - y, dF = 2 r / nb, loss = mean r^2 (one workgroup per member).
-__global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ f, const float *__restrict__ y, int nb,
-                                                   float *__restrict__ dF, float *__restrict__ loss) {
-    __shared__ float red[256];
-    const int z = blockIdx.x;
-    float acc = 0.0f;
-    for (int s = threadIdx.x; s < nb; s += 256) {
-        const float r = f[(int64_t)z * nb + s] - y[(int64_t)z * nb + s];
-        if (dF) dF[(int64_t)z * nb + s] = 2.0f * r / (float)nb;
-        acc += r * r;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss[z] = red[0] / (float)nb;
-}
-
-// Output layer backward: gW3[k] = sum_s dF[s] H2[s][k], gb3 = sum_s dF[s];
-// dZ2[s][k] = dF[s] W3[k] gelu'(Z2[s][k]).
-__global__ void out_bwd_kernel(const float *__restrict__ dF, const float *__restrict__ H2,
-                               const float *__restrict__ Z2, int64_t sHz, int H, const float *__restrict__ params,
-                               float *__restrict__ grad, int64_t P, int64_t offW3, int nb, float *__restrict__ dZ2) {
-    const int z = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const float *W3 = params + z * P + offW3;
-    if (k < H) {
-        float s = 0.0f;
-        for (int t = 0; t < nb; ++t) s += dF[(int64_t)z * nb + t] * H2[z * sHz + (int64_t)t * H + k];
-        grad[z * P + offW3 + k] = s;
-        const float w3 = W3[k];
-        for (int t = 0; t < nb; ++t) {
-            const int64_t o = z * sHz + (int64_t)t * H + k;
-            dZ2[o] = dF[(int64_t)z * nb + t] * w3 * gelu_grad_f(Z2[o]);
-        }
-    } else if (k == H) {
-        float s = 0.0f;
-        for (int t = 0; t < nb; ++t) s += dF[(int64_t)z * nb + t];
-        grad[z * P + offW3 + H] = s;
-    }
-}
-
-// dZ = dH * gelu'(Z), elementwise over [members][nb][H].
-__global__ void gelu_bwd_kernel(const float *__restrict__ dH, const float *__restrict__ Z, int64_t n,
-                                float *__restrict__ dZ) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) dZ[e] = dH[e] * gelu_grad_f(Z[e]);
-}
-
-// grad[z][off + k] = sum_s dZ[z][s][k] (bias gradient).
-__global__ void colsum_kernel(const float *__restrict__ dZ, int64_t sHz, int H, int nb, float *__restrict__ grad,
-                              int64_t P, int64_t off) {
-    const int z = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= H) return;
-    float s = 0.0f;
-    for (int t = 0; t < nb; ++t) s += dZ[z * sHz + (int64_t)t * H + k];
-    grad[z * P + off + k] = s;
-}
-
-// Adam with bias-corrected moments: step t = *step + 1 (the counter lives
-// in device memory so that a captured epoch can be replayed unchanged),
-// c1 = 1 - beta1^t, c2 = 1 - beta2^t.
-__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                            const int64_t *__restrict__ step) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const double t = (double)(*step + 1);
-    const float c1 = (float)(1.0 - pow((double)b1, t));
-    const float c2 = (float)(1.0 - pow((double)b2, t));
-    const float ge = g[e];
-    const float me = b1 * m[e] + (1.0f - b1) * ge;
-    const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
-    m[e] = me;
-    v[e] = ve;
-    p[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
-}
-
-__global__ void tick_kernel(int64_t *step) { *step += 1; }
 
 // Ensemble statistics in logL units (FP64): mean and population spread of
 // y_mean + y_std f_m over the members; with a gate, decision 1 = evaluate
@@ -334,30 +594,32 @@ __global__ __launch_bounds__(CB) void scatter_kernel(const int32_t *__restrict__
 
 struct eor_surrogate {
     int device = 0;
-    int n_in = 0, M = 0, H = 0;
-    int64_t P = 0;                  // parameters per member
+    int n_in = 0, M = 0, H = 0, NT = 0;
+    int64_t P = 0;                  // parameters per member (packed layout of the API)
+    int64_t PP = 0;                 // device stride of a member, P rounded up to 64
     int64_t offW1 = 0, offb1 = 0, offW2 = 0, offb2 = 0, offW3 = 0, offb3 = 0;
     double *d_lo = nullptr, *d_hi = nullptr;   // prior box
     std::vector<double> lo, hi;
     double ymean = 0.0, ystd = 1.0;
     bool trained = false;
     float *params = nullptr, *best = nullptr, *grad = nullptr, *mom = nullptr, *vel = nullptr;
-    // activations for up to cap samples per member
+    float *loss = nullptr;
+    // backward-pass buffers for batches of up to cap samples
     int64_t cap = 0;
-    float *Xb = nullptr, *Yb = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr;
-    float *dZ = nullptr, *dH = nullptr, *f = nullptr, *dF = nullptr, *loss = nullptr;
+    float *H1T = nullptr, *dZ2T = nullptr, *part = nullptr;
+    // forward outputs for up to f_cap samples per member
+    int64_t f_cap = 0;
+    float *f = nullptr;
     // training data (scaled) and indices
     int64_t data_cap = 0;
     float *X = nullptr, *Y = nullptr;
     int32_t *idx = nullptr;
     int64_t idx_cap = 0;
-    int32_t *d_counts = nullptr;
-    int64_t counts_cap = 0;
     uint64_t seed = 0;
     int64_t *d_step = nullptr;      // Adam step count (device)
     hipGraphExec_t epoch_exec = nullptr;  // one captured training epoch
     hipGraph_t epoch_graph = nullptr;
-    int64_t epoch_key[4] = {0, 0, 0, 0};  // (steps, nb, row, n_tr) it was captured for
+    int64_t epoch_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // what it was captured for
     hipStream_t cap_stream = nullptr;
     int epochs_run = 0;
     std::vector<double> best_val;
@@ -390,115 +652,130 @@ void drop_epoch_graph(eor_surrogate &s) {
     std::memset(s.epoch_key, 0, sizeof(s.epoch_key));
 }
 
+int64_t pad16(int64_t n) { return (n + ST - 1) / ST * ST; }
+
 // (Re)allocating any buffer a captured epoch refers to drops that graph.
-hipError_t ensure_act(eor_surrogate &s, int64_t nb) {
+hipError_t ensure_bwd(eor_surrogate &s, int64_t nb) {
     if (s.cap >= nb) return hipSuccess;
     drop_epoch_graph(s);
-    dfree(s.Xb); dfree(s.Yb); dfree(s.Z1); dfree(s.H1); dfree(s.Z2); dfree(s.H2);
-    dfree(s.dZ); dfree(s.dH); dfree(s.f); dfree(s.dF);
+    dfree(s.H1T); dfree(s.dZ2T); dfree(s.part);
     s.cap = 0;
-    const size_t hm = (size_t)s.M * nb * s.H * sizeof(float);
-    hipError_t e = hipMalloc(&s.Xb, (size_t)s.M * nb * s.n_in * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&s.Yb, (size_t)s.M * nb * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&s.Z1, hm);
-    if (e == hipSuccess) e = hipMalloc(&s.H1, hm);
-    if (e == hipSuccess) e = hipMalloc(&s.Z2, hm);
-    if (e == hipSuccess) e = hipMalloc(&s.H2, hm);
-    if (e == hipSuccess) e = hipMalloc(&s.dZ, hm);
-    if (e == hipSuccess) e = hipMalloc(&s.dH, hm);
-    if (e == hipSuccess) e = hipMalloc(&s.f, (size_t)s.M * nb * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&s.dF, (size_t)s.M * nb * sizeof(float));
+    const int64_t nbp = pad16(nb), HP = 64 * (int64_t)s.NT;
+    const size_t hb = (size_t)s.M * HP * nbp * sizeof(float);
+    hipError_t e = hipMalloc(&s.H1T, hb);
+    if (e == hipSuccess) e = hipMalloc(&s.dZ2T, hb);
+    if (e == hipSuccess) e = hipMalloc(&s.part, (size_t)s.M * (nbp / ST) * share_count(s.H, s.n_in) * sizeof(float));
     if (e == hipSuccess) s.cap = nb;
     return e;
 }
 
-void launch_gemm(const GemmArgs &g, int members, hipStream_t st) {
-    dim3 grid((unsigned)((g.N + GT - 1) / GT), (unsigned)((g.M + GT - 1) / GT), (unsigned)members);
-    hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, st, g);
+hipError_t ensure_f(eor_surrogate &s, int64_t n) {
+    if (s.f_cap >= n) return hipSuccess;
+    drop_epoch_graph(s);
+    dfree(s.f);
+    s.f_cap = 0;
+    hipError_t e = hipMalloc(&s.f, (size_t)s.M * n * sizeof(float));
+    if (e == hipSuccess) s.f_cap = n;
+    return e;
 }
 
-// Forward pass of all members on Xb [M][nb][n_in] (per-member inputs when
-// xz_stride != 0, shared inputs when 0): Z1, H1, Z2, H2, f.
-void forward(eor_surrogate &s, const float *Xin, int64_t xz_stride, int nb, hipStream_t st) {
-    const int64_t sHz = (int64_t)nb * s.H;
-    GemmArgs g;
-    std::memset(&g, 0, sizeof(g));
-    // layer 1: Z1[s][h] = sum_k X[s][k] W1[h][k] + b1[h]
-    g.A = Xin; g.sai = s.n_in; g.sak = 1; g.sAz = xz_stride;
-    g.B = s.params + s.offW1; g.sbk = 1; g.sbj = s.n_in; g.sBz = s.P;
-    g.C = s.H1; g.Z = s.Z1; g.ldc = s.H; g.sCz = sHz;
-    g.bias = s.params + s.offb1; g.sbiasz = s.P;
-    g.M = nb; g.N = s.H; g.K = s.n_in; g.epi = 2;
-    launch_gemm(g, s.M, st);
-    // layer 2: Z2[s][h] = sum_k H1[s][k] W2[h][k] + b2[h]
-    g.A = s.H1; g.sai = s.H; g.sak = 1; g.sAz = sHz;
-    g.B = s.params + s.offW2; g.sbk = 1; g.sbj = s.H; g.sBz = s.P;
-    g.C = s.H2; g.Z = s.Z2;
-    g.bias = s.params + s.offb2;
-    g.K = s.H;
-    launch_gemm(g, s.M, st);
-    // output layer
-    const int waves_per_block = 4;
-    hipLaunchKernelGGL(out_fwd_kernel, dim3((unsigned)((nb + waves_per_block - 1) / waves_per_block), (unsigned)s.M),
-                       dim3(64 * waves_per_block), 0, st, s.H2, sHz, s.H, s.params, s.P, s.offW3, nb, s.f);
+MlpArgs net_args(const eor_surrogate &s) {
+    MlpArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.params = s.params;
+    a.PP = s.PP;
+    a.offb1 = s.offb1;
+    a.offW2 = s.offW2;
+    a.offb2 = s.offb2;
+    a.offW3 = s.offW3;
+    a.offb3 = s.offb3;
+    a.n_in = s.n_in;
+    a.H = s.H;
+    return a;
 }
 
-// Loss and gradient of every member on its own batch Xb, Yb (nb samples).
-void backward(eor_surrogate &s, int nb, hipStream_t st) {
-    const int64_t sHz = (int64_t)nb * s.H;
-    hipLaunchKernelGGL(loss_kernel, dim3((unsigned)s.M), dim3(256), 0, st, s.f, s.Yb, nb, s.dF, s.loss);
-    hipLaunchKernelGGL(out_bwd_kernel, dim3((unsigned)((s.H + 1 + 255) / 256), (unsigned)s.M), dim3(256), 0, st,
-                       s.dF, s.H2, s.Z2, sHz, s.H, s.params, s.grad, s.P, s.offW3, nb, s.dZ);
-    GemmArgs g;
-    std::memset(&g, 0, sizeof(g));
-    // gW2[o][i] = sum_s dZ2[s][o] H1[s][i]
-    g.A = s.dZ; g.sai = 1; g.sak = s.H; g.sAz = sHz;
-    g.B = s.H1; g.sbk = s.H; g.sbj = 1; g.sBz = sHz;
-    g.C = s.grad + s.offW2; g.ldc = s.H; g.sCz = s.P;
-    g.M = s.H; g.N = s.H; g.K = nb; g.epi = 0;
-    launch_gemm(g, s.M, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((s.H + 255) / 256), (unsigned)s.M), dim3(256), 0, st, s.dZ,
-                       sHz, s.H, nb, s.grad, s.P, s.offb2);
-    // dH1[s][i] = sum_o dZ2[s][o] W2[o][i]
-    g.A = s.dZ; g.sai = s.H; g.sak = 1; g.sAz = sHz;
-    g.B = s.params + s.offW2; g.sbk = s.H; g.sbj = 1; g.sBz = s.P;
-    g.C = s.dH; g.ldc = s.H; g.sCz = sHz;
-    g.M = nb; g.N = s.H; g.K = s.H;
-    launch_gemm(g, s.M, st);
-    const int64_t nact = (int64_t)s.M * sHz;
-    hipLaunchKernelGGL(gelu_bwd_kernel, dim3((unsigned)((nact + 255) / 256)), dim3(256), 0, st, s.dH, s.Z1, nact,
-                       s.dZ);
-    // gW1[h][k] = sum_s dZ1[s][h] X[s][k]
-    g.A = s.dZ; g.sai = 1; g.sak = s.H; g.sAz = sHz;
-    g.B = s.Xb; g.sbk = s.n_in; g.sbj = 1; g.sBz = (int64_t)nb * s.n_in;
-    g.C = s.grad + s.offW1; g.ldc = s.n_in; g.sCz = s.P;
-    g.M = s.H; g.N = s.n_in; g.K = nb;
-    launch_gemm(g, s.M, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((s.H + 255) / 256), (unsigned)s.M), dim3(256), 0, st, s.dZ,
-                       sHz, s.H, nb, s.grad, s.P, s.offb1);
-}
-
-void adam(eor_surrogate &s, const eor_train_cfg &cfg, hipStream_t st) {
-    const int64_t n = (int64_t)s.M * s.P;
-    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.params, s.grad, s.mom,
-                       s.vel, n, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, s.d_step);
-    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, s.d_step);
-}
-
-// All minibatch steps of one epoch (gather, forward, backward, Adam), for
-// capture into a graph: the indices of the epoch are refreshed in place
-// before every replay, and the Adam step count is read from device memory.
-void epoch_steps(eor_surrogate &s, const eor_train_cfg &cfg, int64_t steps, int nb, int64_t row,
-                 hipStream_t st) {
-    for (int64_t k = 0; k < steps; ++k) {
-        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nb * s.n_in + 255) / 256), (unsigned)s.M), dim3(256), 0,
-                           st, s.X, s.Y, s.n_in, s.idx + k * nb, row, nb, s.Xb, s.Yb);
-        forward(s, s.Xb, (int64_t)nb * s.n_in, nb, st);
-        backward(s, nb, st);
-        adam(s, cfg, st);
+template <int RT, bool BWD>
+void launch_mlp_rt(const MlpArgs &a, int NT, int members, hipStream_t st) {
+    const dim3 grid((unsigned)((a.nb + ST * RT - 1) / (ST * RT)), (unsigned)members), block(256);
+    switch (NT) {
+    case 1: hipLaunchKernelGGL((mlp_kernel<1, RT, BWD>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((mlp_kernel<2, RT, BWD>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((mlp_kernel<3, RT, BWD>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((mlp_kernel<4, RT, BWD>), grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((mlp_kernel<5, RT, BWD>), grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((mlp_kernel<6, RT, BWD>), grid, block, 0, st, a); break;
+    case 7: hipLaunchKernelGGL((mlp_kernel<7, RT, BWD>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((mlp_kernel<8, RT, BWD>), grid, block, 0, st, a); break;
     }
 }
 
+// Forward pass only, 32 samples per workgroup.
+void launch_forward(const MlpArgs &a, int NT, int members, hipStream_t st) {
+    launch_mlp_rt<2, false>(a, NT, members, st);
+}
+
+// Loss, gradient and (with cfg) the Adam step of every member on a batch of
+// nb samples described by `in` (inputs and targets; no outputs).
+void train_step(eor_surrogate &s, MlpArgs in, int nb, const eor_train_cfg *cfg, int64_t step_add, bool write_grad,
+                hipStream_t st) {
+    const int64_t nbp = pad16(nb);
+    in.nb = nb;
+    in.H1T = s.H1T;
+    in.dZ2T = s.dZ2T;
+    in.nbp = nbp;
+    in.part = s.part;
+    in.PS = share_count(s.H, s.n_in);
+    launch_mlp_rt<1, true>(in, s.NT, s.M, st);
+    UpdArgs u;
+    std::memset(&u, 0, sizeof(u));
+    u.H1T = s.H1T;
+    u.dZ2T = s.dZ2T;
+    u.nbp = nbp;
+    u.HP = 64 * s.NT;
+    u.part = s.part;
+    u.PS = in.PS;
+    u.nblk = (int)(nbp / ST);
+    u.H = s.H;
+    u.n_in = s.n_in;
+    u.nb = nb;
+    u.PP = s.PP;
+    u.offb1 = s.offb1;
+    u.offW2 = s.offW2;
+    u.offb2 = s.offb2;
+    u.offW3 = s.offW3;
+    u.offb3 = s.offb3;
+    u.grad = write_grad ? s.grad : nullptr;
+    u.loss = write_grad ? s.loss : nullptr;
+    if (cfg) {
+        u.params = s.params;
+        u.mom = s.mom;
+        u.vel = s.vel;
+        u.lr = cfg->lr;
+        u.b1 = cfg->beta1;
+        u.b2 = cfg->beta2;
+        u.eps = cfg->eps;
+        u.step = s.d_step;
+        u.step_add = step_add;
+    }
+    const int tt = u.HP / 32;
+    const dim3 grid((unsigned)(tt * tt + (in.PS + 255) / 256), (unsigned)s.M);
+    hipLaunchKernelGGL(mlp_update_kernel, grid, dim3(256), 0, st, u);
+}
+
+// All minibatch steps of one epoch, for capture into a graph: the indices of
+// the epoch are refreshed in place before every replay; step k of the epoch
+// uses Adam step count *d_step + k + 1, and the count advances once at the end.
+void epoch_steps(eor_surrogate &s, const eor_train_cfg &cfg, int64_t steps, int nb, int64_t row, hipStream_t st) {
+    MlpArgs in = net_args(s);
+    in.X = s.X;
+    in.Y = s.Y;
+    in.idxz = row;
+    for (int64_t k = 0; k < steps; ++k) {
+        in.idx = s.idx + k * nb;
+        train_step(s, in, nb, &cfg, k, false, st);
+    }
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, st, s.d_step, steps);
+}
 
 void he_init(eor_surrogate &s, std::vector<float> &h) {
     h.assign((size_t)s.M * s.P, 0.0f);
@@ -511,6 +788,13 @@ void he_init(eor_surrogate &s, std::vector<float> &h) {
         for (int64_t k = 0; k < (int64_t)s.H * s.H; ++k) p[s.offW2 + k] = (float)(a2 * nd(rng));
         for (int64_t k = 0; k < s.H; ++k) p[s.offW3 + k] = (float)(a2 * nd(rng));
     }
+}
+
+// packed [M][P] <-> device [M][PP]
+hipError_t copy_params(float *dst, int64_t dst_stride, const float *src, int64_t src_stride, const eor_surrogate &s,
+                       hipMemcpyKind kind, hipStream_t st) {
+    return hipMemcpy2DAsync(dst, (size_t)dst_stride * sizeof(float), src, (size_t)src_stride * sizeof(float),
+                            (size_t)s.P * sizeof(float), (size_t)s.M, kind, st);
 }
 
 eor_status need(const eor_surrogate *s) {
@@ -526,8 +810,10 @@ eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int
                                 const double *lo, const double *hi, eor_surrogate **out) {
     if (!out) return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_create: out is NULL");
     *out = nullptr;
-    if (n_in < 1 || n_in > 1024 || n_members < 1 || n_members > 64 || hidden < 1 || hidden > 4096 || !lo || !hi)
-        return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_create: bad sizes or NULL prior box");
+    if (n_in < 1 || n_in > NI_MAX || n_members < 1 || n_members > 64 || hidden < 4 || hidden > H_MAX ||
+        hidden % 4 != 0 || !lo || !hi)
+        return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_create: need 1 <= n_in <= 64, 1 <= n_members <= 64, "
+                                             "hidden a multiple of 4 in [4, 512] and a prior box");
     for (int k = 0; k < n_in; ++k)
         if (!(hi[k] > lo[k])) return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_create: need hi > lo");
     eor_surrogate *s = new (std::nothrow) eor_surrogate;
@@ -536,6 +822,7 @@ eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int
     s->n_in = n_in;
     s->M = n_members;
     s->H = hidden;
+    s->NT = (hidden + 63) / 64;
     s->seed = seed;
     s->offW1 = 0;
     s->offb1 = s->offW1 + (int64_t)hidden * n_in;
@@ -544,11 +831,12 @@ eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int
     s->offW3 = s->offb2 + hidden;
     s->offb3 = s->offW3 + hidden;
     s->P = s->offb3 + 1;
+    s->PP = (s->P + 63) / 64 * 64;
     s->lo.assign(lo, lo + n_in);
     s->hi.assign(hi, hi + n_in);
     s->best_val.assign(n_members, 0.0);
     DevGuard dg(device);
-    const size_t pb = (size_t)s->M * s->P * sizeof(float);
+    const size_t pb = (size_t)s->M * s->PP * sizeof(float);
     hipError_t e = hipMalloc(&s->params, pb);
     if (e == hipSuccess) e = hipMalloc(&s->best, pb);
     if (e == hipSuccess) e = hipMalloc(&s->grad, pb);
@@ -563,9 +851,13 @@ eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int
     if (e == hipSuccess) e = hipMemcpy(s->d_hi, hi, n_in * sizeof(double), hipMemcpyHostToDevice);
     std::vector<float> h;
     he_init(*s, h);
-    if (e == hipSuccess) e = hipMemcpy(s->params, h.data(), pb, hipMemcpyHostToDevice);
+    // the padding of every member stays zero (parameters, gradient and moments)
+    if (e == hipSuccess) e = hipMemset(s->params, 0, pb);
+    if (e == hipSuccess) e = hipMemset(s->grad, 0, pb);
     if (e == hipSuccess) e = hipMemset(s->mom, 0, pb);
     if (e == hipSuccess) e = hipMemset(s->vel, 0, pb);
+    if (e == hipSuccess) e = copy_params(s->params, s->PP, h.data(), s->P, *s, hipMemcpyHostToDevice, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         eor_surrogate_destroy(s);
         return eor::hip_status(e, "eor_surrogate_create");
@@ -580,9 +872,8 @@ void eor_surrogate_destroy(eor_surrogate *s) {
     (void)hipDeviceSynchronize();
     dfree(s->params); dfree(s->best); dfree(s->grad); dfree(s->mom); dfree(s->vel); dfree(s->loss);
     dfree(s->d_lo); dfree(s->d_hi);
-    dfree(s->Xb); dfree(s->Yb); dfree(s->Z1); dfree(s->H1); dfree(s->Z2); dfree(s->H2);
-    dfree(s->dZ); dfree(s->dH); dfree(s->f); dfree(s->dF);
-    dfree(s->X); dfree(s->Y); dfree(s->idx); dfree(s->d_counts); dfree(s->d_step);
+    dfree(s->H1T); dfree(s->dZ2T); dfree(s->part); dfree(s->f);
+    dfree(s->X); dfree(s->Y); dfree(s->idx); dfree(s->d_step);
     drop_epoch_graph(*s);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
@@ -600,16 +891,16 @@ eor_status eor_surrogate_params(eor_surrogate *s, float *get, const float *set, 
     eor_status st = need(s);
     if (st != EOR_OK) return st;
     DevGuard dg(s->device);
-    const size_t pb = (size_t)s->M * s->P * sizeof(float);
+    const size_t pb = (size_t)s->M * s->PP * sizeof(float);
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     if (set) {
-        e = hipMemcpyAsync(s->params, set, pb, hipMemcpyDeviceToDevice, hs);
+        e = copy_params(s->params, s->PP, set, s->P, *s, hipMemcpyDeviceToDevice, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->mom, 0, pb, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->vel, 0, pb, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->d_step, 0, sizeof(int64_t), hs);
     }
-    if (e == hipSuccess && get) e = hipMemcpyAsync(get, s->params, pb, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess && get) e = copy_params(get, s->P, s->params, s->PP, *s, hipMemcpyDeviceToDevice, hs);
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_params");
 }
 
@@ -636,17 +927,16 @@ eor_status eor_surrogate_loss_grad(eor_surrogate *s, int64_t nb, const float *x,
     if (nb < 1 || nb > (1 << 24) || !x || !y) return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_loss_grad: bad batch");
     DevGuard dg(s->device);
     hipStream_t hs = (hipStream_t)stream;
-    hipError_t e = ensure_act(*s, nb);
+    hipError_t e = ensure_bwd(*s, nb);
     if (e != hipSuccess) return eor::hip_status(e, "surrogate activations");
-    const size_t xb = (size_t)s->M * nb * s->n_in * sizeof(float), yb = (size_t)s->M * nb * sizeof(float);
-    e = hipMemcpyAsync(s->Xb, x, xb, hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->Yb, y, yb, hipMemcpyDeviceToDevice, hs);
-    if (e != hipSuccess) return eor::hip_status(e, "surrogate inputs");
-    forward(*s, s->Xb, (int64_t)nb * s->n_in, (int)nb, hs);
-    backward(*s, (int)nb, hs);
+    MlpArgs in = net_args(*s);
+    in.X = x;
+    in.xz = nb * s->n_in;
+    in.Y = y;
+    in.yz = nb;
+    train_step(*s, in, (int)nb, nullptr, 0, true, hs);
     if (loss) e = hipMemcpyAsync(loss, s->loss, s->M * sizeof(float), hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess && grad)
-        e = hipMemcpyAsync(grad, s->grad, (size_t)s->M * s->P * sizeof(float), hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess && grad) e = copy_params(grad, s->P, s->grad, s->PP, *s, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_loss_grad");
 }
@@ -656,7 +946,11 @@ eor_status eor_surrogate_adam_step(eor_surrogate *s, const eor_train_cfg *cfg, v
     if (st != EOR_OK) return st;
     if (!cfg) return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_adam_step: cfg is NULL");
     DevGuard dg(s->device);
-    adam(*s, *cfg, (hipStream_t)stream);
+    hipStream_t hs = (hipStream_t)stream;
+    const int64_t n = (int64_t)s->M * s->PP;
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, hs, s->params, s->grad, s->mom,
+                       s->vel, n, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, s->d_step);
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, hs, s->d_step, (int64_t)1);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_adam_step");
 }
@@ -724,15 +1018,30 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
         if (e != hipSuccess) return eor::hip_status(e, "index buffer");
         s->idx_cap = s->M * row;
     }
-    e = ensure_act(*s, std::max<int64_t>(nb, n_val));
+    e = ensure_bwd(*s, nb);
+    if (e == hipSuccess) e = ensure_f(*s, std::max<int64_t>(1, n_val));
     if (e != hipSuccess) return eor::hip_status(e, "surrogate activations");
     std::vector<int32_t> hidx((size_t)s->M * row);
     std::vector<float> hloss(s->M);
     std::vector<double> best(s->M, INFINITY);
     std::vector<int> since(s->M, 0);
-    const size_t pb = (size_t)s->M * s->P * sizeof(float);
+    const size_t pb = (size_t)s->M * s->PP * sizeof(float);
     e = hipMemcpyAsync(s->best, s->params, pb, hipMemcpyDeviceToDevice, hs);
     if (e != hipSuccess) return eor::hip_status(e, "best parameters");
+    MlpArgs val = net_args(*s);
+    val.X = s->X;
+    val.Y = s->Y;
+    val.idx = s->idx + n_tr;
+    val.idxz = row;
+    val.nb = (int)n_val;
+    val.f = s->f;
+    val.fz = n_val;
+    // the graph bakes in the shapes and the optimiser's constants
+    int64_t key[8] = {steps, nb, row, n_tr, 0, 0, 0, 0};
+    std::memcpy(&key[4], &cfg->lr, sizeof(float));
+    std::memcpy(&key[5], &cfg->beta1, sizeof(float));
+    std::memcpy(&key[6], &cfg->beta2, sizeof(float));
+    std::memcpy(&key[7], &cfg->eps, sizeof(float));
     int ep = 0;
     for (ep = 0; ep < cfg->epochs; ++ep) {
         for (int z = 0; z < s->M; ++z) {
@@ -742,7 +1051,6 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
         }
         e = hipMemcpyAsync(s->idx, hidx.data(), hidx.size() * sizeof(int32_t), hipMemcpyHostToDevice, hs);
         if (e != hipSuccess) return eor::hip_status(e, "indices");
-        const int64_t key[4] = {steps, nb, row, n_tr};
         if (!s->epoch_exec || std::memcmp(key, s->epoch_key, sizeof(key)) != 0) {
             drop_epoch_graph(*s);
             if (!s->cap_stream) {
@@ -766,14 +1074,11 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
         if (n_val == 0) {
             e = hipStreamSynchronize(hs);
             if (e != hipSuccess) return eor::hip_status(e, "epoch");
+            continue;
         }
-        if (n_val == 0) continue;
-        // validation loss of every member
-        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n_val * s->n_in + 255) / 256), (unsigned)s->M), dim3(256),
-                           0, hs, s->X, s->Y, s->n_in, s->idx + n_tr, row, (int)n_val, s->Xb, s->Yb);
-        forward(*s, s->Xb, n_val * s->n_in, (int)n_val, hs);
-        hipLaunchKernelGGL(loss_kernel, dim3((unsigned)s->M), dim3(256), 0, hs, s->f, s->Yb, (int)n_val, nullptr,
-                           s->loss);
+        // validation loss of every member: residuals, then their mean square
+        launch_forward(val, s->NT, s->M, hs);
+        hipLaunchKernelGGL(loss_kernel, dim3((unsigned)s->M), dim3(256), 0, hs, s->f, (int)n_val, s->loss);
         e = hipMemcpyAsync(hloss.data(), s->loss, s->M * sizeof(float), hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
         if (e != hipSuccess) return eor::hip_status(e, "validation loss");
@@ -782,7 +1087,7 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
             if (hloss[z] < best[z]) {
                 best[z] = hloss[z];
                 since[z] = 0;
-                e = hipMemcpyAsync(s->best + (size_t)z * s->P, s->params + (size_t)z * s->P, s->P * sizeof(float),
+                e = hipMemcpyAsync(s->best + (size_t)z * s->PP, s->params + (size_t)z * s->PP, s->PP * sizeof(float),
                                    hipMemcpyDeviceToDevice, hs);
                 if (e != hipSuccess) return eor::hip_status(e, "best parameters");
             } else {
@@ -832,16 +1137,20 @@ eor_status eor_surrogate_gate(eor_surrogate *s, int64_t B, const double *theta, 
     if (B == 0) return EOR_OK;
     DevGuard dg(s->device);
     hipStream_t hs = (hipStream_t)stream;
-    const int64_t chunk = 65536;
-    hipError_t e = ensure_act(*s, std::min<int64_t>(B, chunk));
-    if (e != hipSuccess) return eor::hip_status(e, "surrogate activations");
+    const int64_t chunk = (int64_t)1 << 20;
+    hipError_t e = ensure_f(*s, std::min<int64_t>(B, chunk));
+    if (e != hipSuccess) return eor::hip_status(e, "surrogate outputs");
     for (int64_t c0 = 0; c0 < B; c0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - c0);
-        // shared inputs for all members
-        hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((nb * s->n_in + 255) / 256)), dim3(256), 0, hs,
-                           theta + c0 * s->n_in, nullptr, (int64_t)nb, s->n_in, s->d_lo, s->d_hi, 0.0, 1.0, s->Xb,
-                           nullptr);
-        forward(*s, s->Xb, 0, nb, hs);
+        // shared inputs for all members, scaled on the fly
+        MlpArgs in = net_args(*s);
+        in.theta = theta + c0 * s->n_in;
+        in.lo = s->d_lo;
+        in.hi = s->d_hi;
+        in.nb = nb;
+        in.f = s->f;
+        in.fz = nb;
+        launch_forward(in, s->NT, s->M, hs);
         if (members)
             for (int z = 0; z < s->M; ++z) {
                 e = hipMemcpyAsync(members + (size_t)z * B + c0, s->f + (size_t)z * nb, nb * sizeof(float),

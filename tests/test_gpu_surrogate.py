@@ -30,7 +30,7 @@ def _params(rng, M, n_in, H):
     return np.stack(ps)
 
 
-@pytest.mark.parametrize("H,nb", [(256, 1024), (64, 333), (37, 50)])
+@pytest.mark.parametrize("H,nb", [(256, 1024), (64, 333), (36, 50), (512, 70)])
 def test_loss_and_gradient_match_oracle(H, nb):
     """FP32 kernels vs the FP64 oracle on the same parameters and batch:
     relative error of every gradient block within 1e-4 of its norm."""
@@ -178,6 +178,12 @@ def test_surrogate_argument_errors():
     hi = np.ones(3)
     assert L.eor_surrogate_create(0, 3, 0, 8, 0, lo.ctypes.data, hi.ctypes.data, ctypes.byref(out)) == eor.EOR_ERR_ARG
     assert L.eor_surrogate_create(0, 3, 2, 8, 0, hi.ctypes.data, lo.ctypes.data, ctypes.byref(out)) == eor.EOR_ERR_ARG
+    # hidden width: a multiple of 4 up to 512; inputs: up to 64
+    assert L.eor_surrogate_create(0, 3, 2, 37, 0, lo.ctypes.data, hi.ctypes.data, ctypes.byref(out)) == eor.EOR_ERR_ARG
+    assert L.eor_surrogate_create(0, 3, 2, 516, 0, lo.ctypes.data, hi.ctypes.data, ctypes.byref(out)) == eor.EOR_ERR_ARG
+    lo65, hi65 = np.zeros(65), np.ones(65)
+    assert L.eor_surrogate_create(0, 65, 2, 8, 0, lo65.ctypes.data, hi65.ctypes.data,
+                                  ctypes.byref(out)) == eor.EOR_ERR_ARG
     s = _sur(3, 2, 8, lo=0.0, hi=1.0)
     # untrained surrogate: inference is refused
     assert L.eor_surrogate_infer(s._h, 4, 1, None, None, None, None) == eor.EOR_ERR_STATE
