@@ -102,12 +102,13 @@ def _matvec_rows(T: np.ndarray, a: np.ndarray, chunk: int = 2048) -> np.ndarray:
 def make_instance(rng: np.random.Generator, m: int, n: int, n_k: int,
                   n_eor: int, n_theta: int, lo: float, hi: float,
                   theta_true=None, shells: bool = False,
-                  T: np.ndarray | None = None) -> Instance:
+                  T: np.ndarray | None = None, bin_of: np.ndarray | None = None) -> Instance:
     """Draw one instance in the fixed order T, sigma^2, a, e, theta."""
     if T is None:
         T = _cn(rng, (m, n), 1.0 / m)          # entries CN(0,1)/sqrt(m)
     noise_var = rng.uniform(0.5, 2.0, size=m)
-    bin_of = shell_bins(n_eor, n, n_k) if shells else balanced_bins(n_eor, n, n_k)
+    if bin_of is None:
+        bin_of = shell_bins(n_eor, n, n_k) if shells else balanced_bins(n_eor, n, n_k)
     fixed_var = np.where(bin_of < 0, FG_VAR, 0.0).astype(np.float64)
     bin_scale = np.ones(n_k, dtype=np.float64)
     if theta_true is None:
@@ -209,3 +210,94 @@ def gen_stress(name: str, seed: int | None = None) -> Instance:
 
 def theta_batch(rng: np.random.Generator, B: int, n_k: int, lo: float, hi: float) -> np.ndarray:
     return np.ascontiguousarray(rng.uniform(lo, hi, size=(B, n_k)))
+
+
+# ---------------------------------------------------------------------------
+# Synthetic instrument: the inputs of the forward model that builds T from a
+# primary beam, the uv sampling and the model's Fourier basis. These are
+# tables of the instrument and of the basis functions; the sum over pixels
+# that turns them into T is not here.
+
+C_LIGHT = 299792458.0
+
+
+@dataclasses.dataclass
+class Instrument:
+    freq: np.ndarray      # float64 (F,), Hz
+    bl: np.ndarray        # float64 (n_bl, 2), baseline east/north in metres
+    lm: np.ndarray        # float64 (n_pix, 2), direction cosines of the sky pixels
+    beam: np.ndarray      # float64 (F, n_pix), primary-beam response
+    uv: np.ndarray        # float64 (n_uv, 2), model Fourier cells in wavelengths
+    Z: np.ndarray         # complex128 (F, n_eta), spectral modes (foreground first)
+    norm: float
+    bin_of: np.ndarray    # int32 (n_eta n_uv,), k-shell of each coefficient, -1 for foreground modes
+    n_k: int
+
+    @property
+    def m(self) -> int:
+        return int(self.freq.size * self.bl.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.Z.shape[1] * self.uv.shape[0])
+
+
+def instrument(seed: int, F: int = 32, n_bl: int = 625, n_side: int = 64, kx: int = 16, ky: int = 8,
+               n_fg: int = 4, n_eor_eta: int = 28, n_k: int = 12, nu0: float = 150e6,
+               dnu: float = 100e3, dish: float = 14.0, fov: float = 0.3) -> Instrument:
+    """Drawn from numpy.random.default_rng(seed): baselines uniform in a
+    disc of radius 60 m (at least 14.6 m long). Fixed: channels nu0 + f dnu;
+    an n_side x n_side pixel grid over a field of view `fov` (radians) centred
+    on the pointing; a Gaussian primary beam of FWHM 1.03 lambda / dish; model
+    cells on the grid's Fourier lattice, kx x ky cells around uv = 0; spectral
+    modes: Legendre polynomials of degree 0..n_fg-1 over the band (foreground)
+    and exp(2 pi i j f / F) for j = +-1 .. +-n_eor_eta/2 (EoR); norm 1/n_pix.
+    EoR coefficients fall into n_k spherical shells of sqrt(ix^2 + iy^2 + j^2)
+    with equal counts (ties kept together)."""
+    rng = np.random.default_rng(seed)
+    r = np.sqrt(rng.uniform((14.6 / 60.0) ** 2, 1.0, size=n_bl)) * 60.0
+    ang = rng.uniform(0.0, 2.0 * np.pi, size=n_bl)
+    bl = np.stack([r * np.cos(ang), r * np.sin(ang)], axis=1)
+    freq = nu0 + dnu * np.arange(F, dtype=np.float64)
+    delta = fov / n_side
+    x = (np.arange(n_side) - n_side // 2) * delta
+    L, M = np.meshgrid(x, x, indexing="xy")
+    lm = np.stack([L.ravel(), M.ravel()], axis=1)
+    sigma = 1.03 * (C_LIGHT / freq) / dish / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+    beam = np.exp(-(lm[None, :, 0] ** 2 + lm[None, :, 1] ** 2) / (2.0 * sigma[:, None] ** 2))
+    du = 1.0 / (n_side * delta)
+    ix, iy = np.meshgrid(np.arange(kx) - kx // 2, np.arange(ky) - ky // 2, indexing="ij")
+    ix, iy = ix.ravel(), iy.ravel()
+    uv = np.stack([ix * du, iy * du], axis=1).astype(np.float64)
+    xf = 2.0 * np.arange(F) / max(F - 1, 1) - 1.0
+    fg = np.stack([np.polynomial.legendre.legval(xf, np.eye(n_fg)[d]) for d in range(n_fg)], axis=1)
+    js = np.concatenate([-np.arange(n_eor_eta // 2, 0, -1), np.arange(1, n_eor_eta // 2 + 1)])
+    eor = np.exp(2j * np.pi * np.outer(np.arange(F), js) / F)
+    Z = np.concatenate([fg.astype(np.complex128), eor], axis=1)
+    n_uv = uv.shape[0]
+    kk = np.sqrt(ix[None, :] ** 2 + iy[None, :] ** 2 + js[:, None] ** 2).ravel()  # EoR coefficients, mode-major
+    order = np.argsort(kk, kind="stable")
+    shell = np.empty(kk.size, dtype=np.int64)
+    shell[order] = (np.arange(kk.size) * n_k) // kk.size
+    # ties kept together: every coefficient takes the shell of the first with its |k|
+    first = {}
+    for idx in order:
+        first.setdefault(kk[idx], shell[idx])
+    shell = np.array([first[v] for v in kk], dtype=np.int64)
+    bin_of = np.concatenate([np.full(n_fg * n_uv, -1, dtype=np.int64), shell]).astype(np.int32)
+    used = np.unique(shell)
+    remap = {b: i for i, b in enumerate(used)}
+    bin_of = np.array([remap[b] if b >= 0 else -1 for b in bin_of], dtype=np.int32)
+    return Instrument(freq=freq, bl=bl, lm=np.ascontiguousarray(lm), beam=np.ascontiguousarray(beam),
+                      uv=uv, Z=np.ascontiguousarray(Z), norm=1.0 / lm.shape[0], bin_of=bin_of,
+                      n_k=int(used.size))
+
+
+def instrument_instance(ins: Instrument, T: np.ndarray, seed: int, n_theta: int, lo: float = -1.0,
+                        hi: float = 3.0) -> Instance:
+    """Noise, data and theta batch for the forward-modelled T (drawn in the
+    same order as make_instance), with the instrument's k-shells."""
+    rng = np.random.default_rng(seed)
+    inst = make_instance(rng, m=T.shape[0], n=T.shape[1], n_k=ins.n_k, n_eor=1, n_theta=n_theta, lo=lo, hi=hi,
+                         T=T, bin_of=ins.bin_of)
+    return inst
