@@ -320,6 +320,34 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
                             double *rows_out, int32_t *index_out, int32_t *count_out, void *stream);
 
 /*
+ * Instrument forward model (the step before the likelihood, from the
+ * instrument model of the paper's "Running BayesEoR" section: a primary-beam
+ * response and the uv sampling of the data). The paper names the inputs but
+ * prints no formula; this is the visibility equation on a pixelised sky
+ * with the sky expanded in the model's basis of 2-D Fourier cells (u_k, v_k)
+ * times spectral modes Z[f][e]:
+ *
+ *   T[f n_bl + b][e n_uv + k] = norm Z[f][e] sum_p A[f][p]
+ *       exp(-2 pi i nu_f / c (x_b l_p + y_b m_p)) exp(2 pi i (u_k l_p + v_k m_p))
+ *
+ * c = 299792458 m/s. All arrays are device memory, row-major:
+ *   freq [n_freq] Hz; bl [n_bl x 2] baseline (x_b, y_b) in metres;
+ *   lm [n_pix x 2] pixel direction cosines; beam [n_freq x n_pix] real
+ *   response A; uv [n_uv x 2] model cells in wavelengths; Z [n_freq x n_eta]
+ *   complex (interleaved re, im); norm: finite scalar.
+ *   T out: complex [n_freq n_bl] rows with leading dimension ldT >= n_eta n_uv
+ *   (complex elements); rows are channel-major, columns spectral-mode-major.
+ * Asynchronous on `stream`; stream-ordered scratch of n_pix n_uv complex.
+ * Errors: EOR_ERR_ARG (sizes < 1, n_freq > 65535, n_bl or n_uv > 65535 x 64,
+ * n_eta > 2^20, n_pix n_uv > 2^34, NULL array, ldT too small, norm not
+ * finite), EOR_ERR_HIP, EOR_ERR_OOM.
+ */
+eor_status eor_forward_model(int64_t n_freq, int64_t n_bl, int64_t n_pix, int64_t n_uv, int64_t n_eta,
+                             const double *freq, const double *bl, const double *lm, const double *beam,
+                             const double *uv, const double *Z, double norm, double *T, int64_t ldT,
+                             void *stream);
+
+/*
  * Measured FP64 matrix peak (for reporting beside the specification peak):
  * back-to-back FP64 16x16x4 MFMAs on independent accumulators, two
  * workgroups of four waves per CU, `iters` rounds of eight per wave, timed on

@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.eor_compact_rows.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P]
         L.eor_probe_fp64_mfma.argtypes = [ctypes.c_int, _I64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
+        L.eor_forward_model.argtypes = [_I64, _I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, ctypes.c_double,
+                                        _P, _I64, _P]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
                      "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
                      "eor_group_set_graph", "eor_group_tuning", "eor_group_set_tuning", "eor_set_tuning",
@@ -103,7 +105,7 @@ def lib() -> ctypes.CDLL:
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
                      "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
-                     "eor_compact_rows", "eor_probe_fp64_mfma"):
+                     "eor_compact_rows", "eor_probe_fp64_mfma", "eor_forward_model"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -398,6 +400,27 @@ def compact_rows(keep, rows=None):
                                  None if out is None else out.data_ptr(), idx.data_ptr(), cnt.data_ptr(), _stream()))
     c = int(cnt.item())
     return (None if out is None else out[:c]), idx[:c], c
+
+
+def forward_model(freq, bl, lm, beam, uv, Z, norm, out=None):
+    """T [F n_bl, n_eta n_uv] complex128 on the GPU from the instrument
+    (freq [F] Hz, bl [n_bl, 2] m, lm [n_pix, 2], beam [F, n_pix]), the model
+    cells uv [n_uv, 2] and spectral modes Z [F, n_eta] (complex): the
+    visibility equation of eor_forward_model."""
+    import torch
+    freq = _dev(freq, torch.float64)
+    bl = _dev(bl, torch.float64)
+    lm = _dev(lm, torch.float64)
+    beam = _dev(beam, torch.float64)
+    uv = _dev(uv, torch.float64)
+    Z = _dev(Z, torch.complex128)
+    F, n_bl, n_pix, n_uv, n_eta = freq.shape[0], bl.shape[0], lm.shape[0], uv.shape[0], Z.shape[1]
+    if out is None:
+        out = torch.empty((F * n_bl, n_eta * n_uv), dtype=torch.complex128, device=freq.device)
+    check(lib().eor_forward_model(F, n_bl, n_pix, n_uv, n_eta, freq.data_ptr(), bl.data_ptr(), lm.data_ptr(),
+                                  beam.data_ptr(), uv.data_ptr(), Z.data_ptr(), float(norm), out.data_ptr(),
+                                  out.stride(0), _stream()))
+    return out
 
 
 def version() -> str:

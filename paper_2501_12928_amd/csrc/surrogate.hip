@@ -119,7 +119,9 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
     __shared__ float r2s[FS];
     const int z = blockIdx.y, s0 = blockIdx.x * FS;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-    const int H = a.H, n_in = a.n_in, nip = (n_in + 15) & ~15, HK = (H + 15) & ~15;
+    // HK: the reduction length over hidden units, H rounded up to 32 (the
+    // LDS rows are zero from H to 64 NT)
+    const int H = a.H, n_in = a.n_in, nip = (n_in + 15) & ~15, HK = (H + 31) & ~31;
     const float *P = a.params + (int64_t)z * a.PP;
     const float *W2 = P + a.offW2;
 
@@ -201,20 +203,25 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
                                     : f4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     };
+    // two groups of 16 k in flight: group g + 32 is read while g is multiplied
+    f4 wb[NT];
     load_w2(0, wv);
-    for (int g = 0; g < HK; g += 16) {
-        f4 wn[NT];
-        load_w2(g + 16, wn);
+    load_w2(16, wb);
+    auto step2 = [&](int g, const f4 *w) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const f4 hv = *reinterpret_cast<const f4 *>(&hs[(ST * rt + l16) * HS + g + 4 * q]);
 #pragma unroll
             for (int c = 0; c < NT; ++c)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) acc[rt][c] = mfma32(hv[t], wv[c][t], acc[rt][c]);
+                for (int t = 0; t < 4; ++t) acc[rt][c] = mfma32(hv[t], w[c][t], acc[rt][c]);
         }
-#pragma unroll
-        for (int c = 0; c < NT; ++c) wv[c] = wn[c];
+    };
+    for (int g = 0; g < HK; g += 32) {
+        step2(g, wv);
+        load_w2(g + 32, wv);
+        step2(g + 16, wb);
+        load_w2(g + 48, wb);
     }
     // output f[s] = sum_o GELU(Z2[s][o]) W3[o] + b3: this wave's units, then
     // the 16 lanes of a group (fixed xor tree), then the four waves in order
@@ -328,19 +335,21 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
                 }
             }
         };
+        float wtb[4][NT];
         load_w2t(0, wt);
-        for (int g = 0; g < HK; g += 16) {
-            float wn[4][NT];
-            load_w2t(g + 16, wn);
+        load_w2t(16, wtb);
+        auto step6 = [&](int g, float (*w)[NT]) {
             const f4 dv = *reinterpret_cast<const f4 *>(&hs[l16 * HS + g + 4 * q]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int c = 0; c < NT; ++c) acc[0][c] = mfma32(dv[t], wt[t][c], acc[0][c]);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int c = 0; c < NT; ++c) wt[t][c] = wn[t][c];
+                for (int c = 0; c < NT; ++c) acc[0][c] = mfma32(dv[t], w[t][c], acc[0][c]);
+        };
+        for (int g = 0; g < HK; g += 32) {
+            step6(g, wt);
+            load_w2t(g + 32, wt);
+            step6(g + 16, wtb);
+            load_w2t(g + 48, wtb);
         }
         // dZ1 = dH1 GELU'(Z1); shares of gb1 and of gW1 = dZ1^T x (the lane's
         // dZ1 values are the A operand of that product as they stand)
@@ -388,9 +397,11 @@ struct UpdArgs {
 };
 
 // Workgroups [0, (HP/32)^2) of member blockIdx.y: a 32 x 32 tile of
-// gW2[o][i] = sum_s dZ2[s][o] H1[s][i] (one 16 x 16 MFMA tile per wave,
-// reduction over the padded batch, whose padding holds dZ2 = 0); the
-// others: 256 consecutive shares each, summed over the blocks in order.
+// gW2[o][i] = sum_s dZ2[s][o] H1[s][i] over the padded batch (whose padding
+// holds dZ2 = 0); each wave sums every fourth group of 16 samples into all
+// four 16 x 16 sub-tiles, then the four partial tiles are added in wave
+// order. The other workgroups: 256 consecutive shares each, summed over the
+// blocks in order.
 __global__ __launch_bounds__(256) void mlp_update_kernel(UpdArgs a) {
     const int z = blockIdx.y, tid = threadIdx.x;
     const int tt = a.HP / 32, ntile = tt * tt;
@@ -398,39 +409,66 @@ __global__ __launch_bounds__(256) void mlp_update_kernel(UpdArgs a) {
     float c1 = 1.0f, c2 = 1.0f;
     if (a.params) adam_factors(a.step, a.step_add, a.b1, a.b2, &c1, &c2);
     if ((int)blockIdx.x < ntile) {
+        __shared__ f4 red[4][4][64];  // [wave][16 x 16 sub-tile][lane]
         const int lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-        const int o0 = 32 * ((int)blockIdx.x / tt) + 16 * (w & 1);
-        const int i0 = 32 * ((int)blockIdx.x % tt) + 16 * (w >> 1);
-        const float *Ar = a.dZ2T + ((int64_t)z * a.HP + o0 + l16) * a.nbp + 4 * q;
-        const float *Br = a.H1T + ((int64_t)z * a.HP + i0 + l16) * a.nbp + 4 * q;
-        f4 acc = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        int64_t k0 = 0;
-        for (; k0 + 64 <= a.nbp; k0 += 64) {
-            f4 av[4], bv[4];
+        const int o0 = 32 * ((int)blockIdx.x / tt), i0 = 32 * ((int)blockIdx.x % tt);
+        const float *A0 = a.dZ2T + ((int64_t)z * a.HP + o0 + l16) * a.nbp + 4 * q;
+        const float *A1 = A0 + 16 * a.nbp;
+        const float *B0 = a.H1T + ((int64_t)z * a.HP + i0 + l16) * a.nbp + 4 * q;
+        const float *B1 = B0 + 16 * a.nbp;
+        // sub-tile j = 2 oh + ih covers rows o0 + 16 oh, columns i0 + 16 ih
+        f4 acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        // wave w takes the groups of 16 samples g = w, w + 4, ..., four in flight
+        const int ng = (int)(a.nbp / 16);
+        int g = w;
+        for (; g + 12 < ng; g += 16) {
+            f4 av[4][2], bv[4][2];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = *reinterpret_cast<const f4 *>(Ar + k0 + 16 * u);
-                bv[u] = *reinterpret_cast<const f4 *>(Br + k0 + 16 * u);
+                const int64_t k = 16 * (int64_t)(g + 4 * u);
+                av[u][0] = *reinterpret_cast<const f4 *>(A0 + k);
+                av[u][1] = *reinterpret_cast<const f4 *>(A1 + k);
+                bv[u][0] = *reinterpret_cast<const f4 *>(B0 + k);
+                bv[u][1] = *reinterpret_cast<const f4 *>(B1 + k);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) acc = mfma32(av[u][t], bv[u][t], acc);
-        }
-        for (; k0 < a.nbp; k0 += 16) {
-            const f4 av = *reinterpret_cast<const f4 *>(Ar + k0);
-            const f4 bv = *reinterpret_cast<const f4 *>(Br + k0);
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc = mfma32(av[t], bv[t], acc);
+                    for (int t = 0; t < 4; ++t) acc[j] = mfma32(av[u][j >> 1][t], bv[u][j & 1][t], acc[j]);
         }
-        const int i = i0 + l16;
+        for (; g < ng; g += 4) {
+            const int64_t k = 16 * (int64_t)g;
+            const f4 av0 = *reinterpret_cast<const f4 *>(A0 + k), av1 = *reinterpret_cast<const f4 *>(A1 + k);
+            const f4 bv0 = *reinterpret_cast<const f4 *>(B0 + k), bv1 = *reinterpret_cast<const f4 *>(B1 + k);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                acc[0] = mfma32(av0[t], bv0[t], acc[0]);
+                acc[1] = mfma32(av0[t], bv1[t], acc[1]);
+                acc[2] = mfma32(av1[t], bv0[t], acc[2]);
+                acc[3] = mfma32(av1[t], bv1[t], acc[3]);
+            }
+        }
+        // fixed-order sum over the waves; wave w finishes sub-tile w
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[w][j][lane] = acc[j];
+        __syncthreads();
+        f4 sum = red[0][w][lane];
+        sum += red[1][w][lane];
+        sum += red[2][w][lane];
+        sum += red[3][w][lane];
+        // lane holds gW2[o0 + 16 (w >> 1) + 4 q + r][i0 + 16 (w & 1) + l16]
+        const int i = i0 + 16 * (w & 1) + l16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int o = o0 + 4 * q + r;
+            const int o = o0 + 16 * (w >> 1) + 4 * q + r;
             if (o < a.H && i < a.H) {
                 const int64_t e = zp + a.offW2 + (int64_t)o * a.H + i;
-                if (a.grad) a.grad[e] = acc[r];
-                if (a.params) adam_update(&a.params[e], acc[r], &a.mom[e], &a.vel[e], a.lr, a.b1, a.b2, a.eps, c1, c2);
+                if (a.grad) a.grad[e] = sum[r];
+                if (a.params) adam_update(&a.params[e], sum[r], &a.mom[e], &a.vel[e], a.lr, a.b1, a.b2, a.eps, c1, c2);
             }
         }
         return;

@@ -5,6 +5,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -44,6 +45,13 @@ def test_argument_errors_without_gpu():
     assert L.eor_loglike_batch(None, 1, None, None, None, None) == eor.EOR_ERR_ARG
     assert L.eor_precompute(None, 1, 1, None, 1, None, None, 0, None, None, None, 0, None) == eor.EOR_ERR_ARG
     assert eor.version().startswith("eor")
+    # forward model: sizes, NULL arrays, leading dimension, norm (refused before any device work)
+    x = np.zeros(4)
+    p = x.ctypes.data
+    assert L.eor_forward_model(0, 1, 1, 1, 1, p, p, p, p, p, p, 1.0, p, 1, None) == eor.EOR_ERR_ARG
+    assert L.eor_forward_model(1, 1, 1, 2, 2, p, p, p, p, p, p, 1.0, p, 3, None) == eor.EOR_ERR_ARG
+    assert L.eor_forward_model(1, 1, 1, 1, 1, p, None, p, p, p, p, 1.0, p, 1, None) == eor.EOR_ERR_ARG
+    assert L.eor_forward_model(1, 1, 1, 1, 1, p, p, p, p, p, p, float("inf"), p, 1, None) == eor.EOR_ERR_ARG
 
 
 def test_product_package_does_not_reference_oracle():

@@ -1,0 +1,92 @@
+"""GPU forward model (eor_forward_model) against the FP64 oracle
+(oracle/forward_model.py): element by element on small ragged shapes (pixel
+count not a multiple of the 16-pixel stage, baselines and uv cells not
+multiples of the 64 x 64 tile, a padded leading dimension), the degenerate
+1 x 1 case, sampled entries of the full 20000 x 4096 synthetic instrument,
+and the likelihood of data seen through a forward-modelled T."""
+import numpy as np
+import pytest
+
+from oracle import forward_model as fm
+from tests.gpu_util import have_gpu, tol
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="no GPU")]
+
+
+def _random_instrument(rng, F, n_bl, n_pix, n_uv, n_eta):
+    freq = 140e6 + 1e5 * np.arange(F) + rng.uniform(0, 5e4, size=F)
+    bl = rng.uniform(-60.0, 60.0, size=(n_bl, 2))
+    lm = rng.uniform(-0.2, 0.2, size=(n_pix, 2))
+    beam = rng.uniform(0.05, 1.0, size=(F, n_pix))
+    uv = rng.uniform(-20.0, 20.0, size=(n_uv, 2))
+    Z = rng.standard_normal((F, n_eta)) + 1j * rng.standard_normal((F, n_eta))
+    return freq, bl, lm, beam, uv, Z
+
+
+@pytest.mark.parametrize("F,n_bl,n_pix,n_uv,n_eta", [(3, 70, 300, 80, 5), (2, 129, 17, 64, 3), (1, 1, 1, 1, 1)])
+def test_forward_model_matches_oracle(F, n_bl, n_pix, n_uv, n_eta):
+    import torch
+    import paper_2501_12928_amd as eor
+    rng = np.random.default_rng(F * 1000 + n_bl)
+    freq, bl, lm, beam, uv, Z = _random_instrument(rng, F, n_bl, n_pix, n_uv, n_eta)
+    norm = 1.0 / n_pix
+    ref = fm.forward_model(freq, bl, lm, beam, uv, Z, norm)
+    # padded leading dimension: the three extra columns of every row stay untouched
+    ld = n_eta * n_uv + 3
+    buf = torch.full((F * n_bl, ld), complex("nan"), dtype=torch.complex128, device="cuda")
+    print(f"gpu: forward model F={F} n_bl={n_bl} n_pix={n_pix} n_uv={n_uv} n_eta={n_eta}", flush=True)
+    eor.forward_model(freq, bl, lm, beam, uv, Z, norm, out=buf[:, :n_eta * n_uv])
+    got = buf.cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got[:, :n_eta * n_uv] - ref)) <= 1e-11 * scale
+    assert np.all(np.isnan(got[:, n_eta * n_uv:]))
+
+
+def test_forward_model_full_instrument_sampled():
+    """The 20000 x 4096 synthetic instrument (32 channels, 625 baselines,
+    64 x 64 pixels, 128 uv cells, 4 foreground + 28 EoR spectral modes):
+    400 entries against the oracle's pixel sum."""
+    import torch
+    import synth
+    import paper_2501_12928_amd as eor
+    ins = synth.instrument(5)
+    print("gpu: forward model 20000 x 4096", flush=True)
+    T = eor.forward_model(ins.freq, ins.bl, ins.lm, ins.beam, ins.uv, ins.Z, ins.norm)
+    torch.cuda.synchronize()
+    assert T.shape == (ins.m, ins.n)
+    rng = np.random.default_rng(6)
+    rows = rng.integers(0, ins.m, size=400)
+    cols = rng.integers(0, ins.n, size=400)
+    got = T[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = np.array([fm.forward_model_entry(ins.freq, ins.bl, ins.lm, ins.beam, ins.uv, ins.Z, ins.norm, r, c)
+                    for r, c in zip(rows, cols)])
+    # an entry is a sum of 4096 terms of size <= norm: absolute bound
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    assert bool(torch.isfinite(torch.view_as_real(T)).all().item())
+
+
+def test_likelihood_through_forward_model():
+    """Data seen through a forward-modelled instrument (8 channels, 60
+    baselines, 16 x 16 pixels, 32 uv cells, 2 foreground + 6 EoR spectral
+    modes; m = 480, n = 256): the GPU builds its own T and evaluates logL,
+    the oracle does both steps on its own T."""
+    import torch
+    import oracle
+    import synth
+    import paper_2501_12928_amd as eor
+    ins = synth.instrument(21, F=8, n_bl=60, n_side=16, kx=8, ky=4, n_fg=2, n_eor_eta=6, n_k=4)
+    T_ref = fm.forward_model(ins.freq, ins.bl, ins.lm, ins.beam, ins.uv, ins.Z, ins.norm)
+    inst = synth.instrument_instance(ins, T_ref, seed=22, n_theta=24)
+    ref, info_ref = oracle.get().loglike_instance(inst)
+    assert np.all(info_ref == 0)
+    print("gpu: likelihood through the forward model, m=480 n=256", flush=True)
+    T = eor.forward_model(ins.freq, ins.bl, ins.lm, ins.beam, ins.uv, ins.Z, ins.norm)
+    ctx = eor.Context(0)
+    ctx.precompute(T, torch.from_numpy(inst.noise_var).cuda(), torch.from_numpy(inst.d).cuda(), inst.n_k,
+                   inst.bin_of, inst.fixed_var, inst.bin_scale)
+    logL, info = ctx.loglike_batch(torch.from_numpy(inst.theta).cuda())
+    torch.cuda.synchronize()
+    logL = logL.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    assert np.all(np.abs(logL - ref) <= tol(ref))
+    ctx.close()
