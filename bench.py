@@ -314,6 +314,59 @@ def bench_gated(args):
     ctx.close()
 
 
+def bench_instrument(args):
+    """The path on data seen through a forward-modelled instrument: T built
+    on the GPU (eor_forward_model) from the synthetic instrument (32 channels
+    x 625 baselines = 20000 visibilities; 128 uv cells x (4 foreground + 28
+    EoR) spectral modes = 4096 coefficients, 12 k-shells; 64 x 64 sky
+    pixels, Gaussian beam), then the precompute and one likelihood batch of
+    B = 512 theta. The data vector is drawn from the GPU-built T on the host."""
+    import torch
+    import synth
+    import paper_2501_12928_amd as eor
+    ins = synth.instrument(5)
+    args_fm = (ins.freq, ins.bl, ins.lm, ins.beam, ins.uv, ins.Z, ins.norm)
+    T = eor.forward_model(*args_fm)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+    dev_in = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in args_fm[:6]]
+    for a, b in ev:
+        a.record(stream)
+        eor.forward_model(*dev_in, ins.norm, out=T)
+        b.record(stream)
+    torch.cuda.synchronize()
+    fm_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    F, n_bl, n_pix, n_uv = ins.freq.size, ins.bl.shape[0], ins.lm.shape[0], ins.uv.shape[0]
+    fm_flop = 8.0 * F * n_bl * n_pix * n_uv
+    inst = synth.instrument_instance(ins, T.cpu().numpy(), seed=7, n_theta=512)
+    ctx = eor.Context(0)
+    nv = torch.from_numpy(inst.noise_var).cuda()
+    d = torch.from_numpy(inst.d).cuda()
+    theta = torch.from_numpy(inst.theta).cuda()
+    ctx.precompute(T, nv, d, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale)
+    logL, info = ctx.loglike_batch(theta)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.loglike_batch(theta, out=logL, info=info)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    like_ms = e0.elapsed_time(e1)
+    print(json.dumps({
+        "metric": "logL evals/s at n=4096 complex FP64 on a forward-modelled instrument (report)",
+        "value": theta.shape[0] / (like_ms / 1e3), "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"T from the forward model: {F} channels x {n_bl} baselines, {n_uv} uv cells x "
+                               f"{ins.Z.shape[1]} spectral modes, {n_pix} pixels, Gaussian beam; "
+                               f"{ins.n_k} k-shells; B=512 theta"},
+        "forward_model_ms": fm_ms, "forward_model_tflops": fm_flop / (fm_ms / 1e3) / 1e12,
+        "forward_model_write_gbs": ins.m * ins.n * 16 / (fm_ms / 1e3) / 1e9,
+        "loglike_ms": like_ms, "info_nonzero": int((info != 0).sum().item()),
+        "logL_range": [float(logL.min().item()), float(logL.max().item())]}))
+    ctx.close()
+
+
 def surrogate_flops(n_in: int, H: int):
     """(inference, training) FP32 flop per sample and member of an
     n_in -> H -> H -> 1 network: the forward pass is its three dense layers;
@@ -411,11 +464,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
-    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress", "surrogate"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress", "surrogate", "instrument"], default="metric",
                     help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances; "
                          "gated: nested sampling at 20000x4096 without and with the surrogate gate; "
                          "stress: reduced precision on ill-conditioned instruments at 8000x2048; "
-                         "surrogate: ensemble training on 1e5 samples and gating of 1e6 proposals")
+                         "surrogate: ensemble training on 1e5 samples and gating of 1e6 proposals; "
+                         "instrument: T from the forward model, then precompute and one batch")
     ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
     ap.add_argument("--n-live", type=int, default=500)
     ap.add_argument("--first-train", type=int, default=30000)
@@ -466,6 +520,8 @@ def main():
         return bench_stress(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "instrument":
+        return bench_instrument(args)
 
     inst = synth.gen(CONFIG_ID)
     B, n, m = inst.theta.shape[0], inst.n, inst.m
