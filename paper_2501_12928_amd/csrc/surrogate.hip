@@ -13,7 +13,7 @@
 // standardised by the training mean and standard deviation.
 //
 // One training step is two kernels:
-//  - mlp_kernel<NT, 1, true>: one workgroup per 16 samples of one member
+//  - mlp_kernel<CT, 8, 1, true>: one workgroup per 16 samples of one member
 //    gathers its inputs, runs both hidden layers, the output, the loss and
 //    the backward pass down to dZ1 with the activations in LDS and
 //    registers (FP32 MFMA 16x16x4), writes H1^T and dZ2^T (the operands of
@@ -89,7 +89,7 @@ struct MlpArgs {
     // forward only: f[z fz + s] = network output, minus the target when Y is set
     float *f;
     int64_t fz;
-    // backward: H1T, dZ2T [z][64 NT][nbp]; part [z][block][PS]
+    // backward: H1T, dZ2T [z][padded width][nbp]; part [z][block][PS]
     float *H1T, *dZ2T;
     int64_t nbp;
     float *part;
@@ -100,32 +100,32 @@ struct MlpArgs {
 // gb1 [H], gb2 [H], gW3 [H], gb3, and the block's sum of squared residuals.
 __host__ __device__ inline int64_t share_count(int H, int n_in) { return (int64_t)H * n_in + 3 * (int64_t)H + 2; }
 
-// One workgroup of four waves per RT * 16 samples of member blockIdx.y;
-// wave w owns hidden units [16 NT w, 16 NT (w + 1)) of both layers (the
-// hidden width is padded to 64 NT; padded units carry zero weights and stay
+// One workgroup of NW waves per RT * 16 samples of member blockIdx.y; wave
+// w owns hidden units [16 CT w, 16 CT (w + 1)) of both layers (the hidden
+// width is padded to 16 CT NW; padded units carry zero weights and stay
 // exactly zero). In an MFMA step t, lane group q = lane / 16 supplies the
 // operand pair of reduction index 4 q + t within a group of 16, for A and
 // B alike, so that each lane loads four consecutive k with one 16-byte read.
-template <int NT, int RT, bool BWD>
-__global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
+template <int CT, int NW, int RT, bool BWD>
+__global__ __launch_bounds__(64 * NW) void mlp_kernel(MlpArgs a) {
     static_assert(!BWD || RT == 1, "the backward pass takes 16 samples per workgroup");
     constexpr int FS = ST * RT;       // samples per workgroup
-    constexpr int HP = 64 * NT;
+    constexpr int HP = 16 * CT * NW;
     constexpr int HS = HP + 4;        // LDS row stride of the hidden activations
     __shared__ __align__(16) float xs[FS * XS];
     __shared__ __align__(16) float hs[FS * HS];
-    __shared__ float fpart[4 * FS];
+    __shared__ float fpart[NW * FS];
     __shared__ float dfs[FS];
     __shared__ float r2s[FS];
     const int z = blockIdx.y, s0 = blockIdx.x * FS;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
     // HK: the reduction length over hidden units, H rounded up to 32 (the
-    // LDS rows are zero from H to 64 NT)
+    // LDS rows are zero from H to 16 CT NW)
     const int H = a.H, n_in = a.n_in, nip = (n_in + 15) & ~15, HK = (H + 31) & ~31;
     const float *P = a.params + (int64_t)z * a.PP;
     const float *W2 = P + a.offW2;
 
-    for (int e = tid; e < FS * nip; e += 256) {
+    for (int e = tid; e < FS * nip; e += 64 * NW) {
         const int s = e / nip, k = e - s * nip, gs = s0 + s;
         float v = 0.0f;
         if (k < n_in && gs < a.nb) {
@@ -139,17 +139,17 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
     }
     __syncthreads();
 
-    const int hb = 16 * NT * w;
-    f4 acc[RT][NT];
+    const int hb = 16 * CT * w;
+    f4 acc[RT][CT];
     // layer 1: Z1[s][h] = sum_k x[s][k] W1[h][k] + b1[h]
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int c = 0; c < NT; ++c) acc[rt][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int g = 0; g < nip; g += 16) {
-        float wv[NT][4];
+        float wv[CT][4];
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
+        for (int c = 0; c < CT; ++c) {
             const int h = hb + 16 * c + l16;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -161,15 +161,15 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
         for (int rt = 0; rt < RT; ++rt) {
             const f4 xv = *reinterpret_cast<const f4 *>(&xs[(ST * rt + l16) * XS + g + 4 * q]);
 #pragma unroll
-            for (int c = 0; c < NT; ++c)
+            for (int c = 0; c < CT; ++c)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc[rt][c] = mfma32(xv[t], wv[c][t], acc[rt][c]);
         }
     }
     // lane holds Z1[16 rt + 4 q + r][hb + 16 c + l16]
-    f4 g1[BWD ? NT : 1];
+    f4 g1[BWD ? CT : 1];
 #pragma unroll
-    for (int c = 0; c < NT; ++c) {
+    for (int c = 0; c < CT; ++c) {
         const int h = hb + 16 * c + l16;
         const float b = h < H ? P[a.offb1 + h] : 0.0f;
 #pragma unroll
@@ -191,20 +191,20 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int c = 0; c < NT; ++c) acc[rt][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     // W2 reads run one group of 16 k ahead of the MFMAs that use them
-    f4 wv[NT];
+    f4 wv[CT];
     auto load_w2 = [&](int g, f4 *dst) {
         const bool kin = g + 4 * q < H;
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
+        for (int c = 0; c < CT; ++c) {
             const int o = hb + 16 * c + l16;
             dst[c] = (o < H && kin) ? *reinterpret_cast<const f4 *>(&W2[(int64_t)o * H + g + 4 * q])
                                     : f4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     };
     // two groups of 16 k in flight: group g + 32 is read while g is multiplied
-    f4 wb[NT];
+    f4 wb[CT];
     load_w2(0, wv);
     load_w2(16, wb);
     auto step2 = [&](int g, const f4 *w) {
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
         for (int rt = 0; rt < RT; ++rt) {
             const f4 hv = *reinterpret_cast<const f4 *>(&hs[(ST * rt + l16) * HS + g + 4 * q]);
 #pragma unroll
-            for (int c = 0; c < NT; ++c)
+            for (int c = 0; c < CT; ++c)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc[rt][c] = mfma32(hv[t], w[c][t], acc[rt][c]);
         }
@@ -224,15 +224,15 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
         load_w2(g + 48, wb);
     }
     // output f[s] = sum_o GELU(Z2[s][o]) W3[o] + b3: this wave's units, then
-    // the 16 lanes of a group (fixed xor tree), then the four waves in order
-    f4 h2[BWD ? NT : 1], gw[BWD ? NT : 1];
+    // the 16 lanes of a group (fixed xor tree), then the waves in order
+    f4 h2[BWD ? CT : 1], gw[BWD ? CT : 1];
     float fp[RT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) fp[rt][r] = 0.0f;
 #pragma unroll
-    for (int c = 0; c < NT; ++c) {
+    for (int c = 0; c < CT; ++c) {
         const int o = hb + 16 * c + l16;
         const float b = o < H ? P[a.offb2 + o] : 0.0f;
         const float w3 = o < H ? P[a.offW3 + o] : 0.0f;
@@ -264,9 +264,8 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
     if (tid < FS) {
         const int s = tid, gs = s0 + s;
         float f = fpart[s];
-        f += fpart[FS + s];
-        f += fpart[2 * FS + s];
-        f += fpart[3 * FS + s];
+#pragma unroll
+        for (int v = 1; v < NW; ++v) f += fpart[v * FS + s];
         f += P[a.offb3];
         const bool valid = gs < a.nb;
         float res = 0.0f;
@@ -287,7 +286,7 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
         __syncthreads();
         // dZ2 = dF W3 GELU'(Z2): into LDS (the A operand of dH1) and dZ2^T
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
+        for (int c = 0; c < CT; ++c) {
             const int o = hb + 16 * c + l16;
             f4 d;
 #pragma unroll
@@ -322,28 +321,28 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
         __syncthreads();
         // dH1[s][i] = sum_o dZ2[s][o] W2[o][i]
 #pragma unroll
-        for (int c = 0; c < NT; ++c) acc[0][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        float wt[4][NT];
-        auto load_w2t = [&](int g, float (*dst)[NT]) {
+        for (int c = 0; c < CT; ++c) acc[0][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        float wt[4][CT];
+        auto load_w2t = [&](int g, float (*dst)[CT]) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int o = g + 4 * q + t;
 #pragma unroll
-                for (int c = 0; c < NT; ++c) {
+                for (int c = 0; c < CT; ++c) {
                     const int i = hb + 16 * c + l16;
                     dst[t][c] = (o < H && i < H) ? W2[(int64_t)o * H + i] : 0.0f;
                 }
             }
         };
-        float wtb[4][NT];
+        float wtb[4][CT];
         load_w2t(0, wt);
         load_w2t(16, wtb);
-        auto step6 = [&](int g, float (*w)[NT]) {
+        auto step6 = [&](int g, float (*w)[CT]) {
             const f4 dv = *reinterpret_cast<const f4 *>(&hs[l16 * HS + g + 4 * q]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int c = 0; c < NT; ++c) acc[0][c] = mfma32(dv[t], w[t][c], acc[0][c]);
+                for (int c = 0; c < CT; ++c) acc[0][c] = mfma32(dv[t], w[t][c], acc[0][c]);
         };
         for (int g = 0; g < HK; g += 32) {
             step6(g, wt);
@@ -354,7 +353,7 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a) {
         // dZ1 = dH1 GELU'(Z1); shares of gb1 and of gW1 = dZ1^T x (the lane's
         // dZ1 values are the A operand of that product as they stand)
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
+        for (int c = 0; c < CT; ++c) {
             const int h = hb + 16 * c + l16;
             f4 d1;
 #pragma unroll
@@ -478,7 +477,15 @@ __global__ __launch_bounds__(256) void mlp_update_kernel(UpdArgs a) {
     if (e > ns) return;
     const float *pp = a.part + (int64_t)z * a.nblk * a.PS + e;
     float g = 0.0f;
-    for (int b = 0; b < a.nblk; ++b) g += pp[(int64_t)b * a.PS];
+    int b = 0;
+    for (; b + 8 <= a.nblk; b += 8) {  // eight reads in flight, added in block order
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)(b + u) * a.PS];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g += v[u];
+    }
+    for (; b < a.nblk; ++b) g += pp[(int64_t)b * a.PS];
     if (e == ns) {
         if (a.loss) a.loss[z] = g / (float)a.nb;
         return;
@@ -632,7 +639,9 @@ __global__ __launch_bounds__(CB) void scatter_kernel(const int32_t *__restrict__
 
 struct eor_surrogate {
     int device = 0;
-    int n_in = 0, M = 0, H = 0, NT = 0;
+    int n_in = 0, M = 0, H = 0;
+    int NT = 0;   // forward: four waves of NT 16-unit tiles (width 64 NT)
+    int CTB = 0;  // backward: eight waves of CTB tiles (width 128 CTB)
     int64_t P = 0;                  // parameters per member (packed layout of the API)
     int64_t PP = 0;                 // device stride of a member, P rounded up to 64
     int64_t offW1 = 0, offb1 = 0, offW2 = 0, offb2 = 0, offW3 = 0, offb3 = 0;
@@ -698,7 +707,7 @@ hipError_t ensure_bwd(eor_surrogate &s, int64_t nb) {
     drop_epoch_graph(s);
     dfree(s.H1T); dfree(s.dZ2T); dfree(s.part);
     s.cap = 0;
-    const int64_t nbp = pad16(nb), HP = 64 * (int64_t)s.NT;
+    const int64_t nbp = pad16(nb), HP = 128 * (int64_t)s.CTB;
     const size_t hb = (size_t)s.M * HP * nbp * sizeof(float);
     hipError_t e = hipMalloc(&s.H1T, hb);
     if (e == hipSuccess) e = hipMalloc(&s.dZ2T, hb);
@@ -732,24 +741,33 @@ MlpArgs net_args(const eor_surrogate &s) {
     return a;
 }
 
-template <int RT, bool BWD>
-void launch_mlp_rt(const MlpArgs &a, int NT, int members, hipStream_t st) {
-    const dim3 grid((unsigned)((a.nb + ST * RT - 1) / (ST * RT)), (unsigned)members), block(256);
-    switch (NT) {
-    case 1: hipLaunchKernelGGL((mlp_kernel<1, RT, BWD>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((mlp_kernel<2, RT, BWD>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((mlp_kernel<3, RT, BWD>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((mlp_kernel<4, RT, BWD>), grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL((mlp_kernel<5, RT, BWD>), grid, block, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((mlp_kernel<6, RT, BWD>), grid, block, 0, st, a); break;
-    case 7: hipLaunchKernelGGL((mlp_kernel<7, RT, BWD>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((mlp_kernel<8, RT, BWD>), grid, block, 0, st, a); break;
+template <int NW, int RT, bool BWD>
+void launch_mlp(const MlpArgs &a, int CT, int members, hipStream_t st) {
+    const dim3 grid((unsigned)((a.nb + ST * RT - 1) / (ST * RT)), (unsigned)members), block(64 * NW);
+    if constexpr (NW == 8) {  // widths up to 512 in tiles of 128
+        switch (CT) {
+        case 1: hipLaunchKernelGGL((mlp_kernel<1, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((mlp_kernel<2, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((mlp_kernel<3, NW, RT, BWD>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((mlp_kernel<4, NW, RT, BWD>), grid, block, 0, st, a); break;
+        }
+    } else {                  // widths up to 512 in tiles of 64
+        switch (CT) {
+        case 1: hipLaunchKernelGGL((mlp_kernel<1, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((mlp_kernel<2, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((mlp_kernel<3, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((mlp_kernel<4, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((mlp_kernel<5, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((mlp_kernel<6, NW, RT, BWD>), grid, block, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((mlp_kernel<7, NW, RT, BWD>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((mlp_kernel<8, NW, RT, BWD>), grid, block, 0, st, a); break;
+        }
     }
 }
 
-// Forward pass only, 32 samples per workgroup.
+// Forward pass only: four waves, 32 samples per workgroup.
 void launch_forward(const MlpArgs &a, int NT, int members, hipStream_t st) {
-    launch_mlp_rt<2, false>(a, NT, members, st);
+    launch_mlp<4, 2, false>(a, NT, members, st);
 }
 
 // Loss, gradient and (with cfg) the Adam step of every member on a batch of
@@ -763,13 +781,13 @@ void train_step(eor_surrogate &s, MlpArgs in, int nb, const eor_train_cfg *cfg, 
     in.nbp = nbp;
     in.part = s.part;
     in.PS = share_count(s.H, s.n_in);
-    launch_mlp_rt<1, true>(in, s.NT, s.M, st);
+    launch_mlp<8, 1, true>(in, s.CTB, s.M, st);
     UpdArgs u;
     std::memset(&u, 0, sizeof(u));
     u.H1T = s.H1T;
     u.dZ2T = s.dZ2T;
     u.nbp = nbp;
-    u.HP = 64 * s.NT;
+    u.HP = 128 * s.CTB;
     u.part = s.part;
     u.PS = in.PS;
     u.nblk = (int)(nbp / ST);
@@ -861,6 +879,7 @@ eor_status eor_surrogate_create(int device, int32_t n_in, int32_t n_members, int
     s->M = n_members;
     s->H = hidden;
     s->NT = (hidden + 63) / 64;
+    s->CTB = (hidden + 127) / 128;
     s->seed = seed;
     s->offW1 = 0;
     s->offb1 = s->offW1 + (int64_t)hidden * n_in;
