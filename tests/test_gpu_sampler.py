@@ -32,6 +32,8 @@ def test_gated_sampler_agrees_with_plain(orc):
     assert abs(cmp["logz_plain"] - cmp["logz_gated"]) < cmp["logz_tolerance"]
     assert cmp["max_dmean_over_sigma"] < 0.25
     assert cmp["gate_rejected"] > 0
+    # what the trained network gains: exact calls the plain run makes and the gated one does not
+    assert cmp["exact_calls_gated"] < cmp["exact_calls_plain"]
     assert cmp["false_rejections"] <= 0.05 * max(cmp["audited"], 1) + 1
     # accepted points carry exact logL: check a sample against the oracle
     idx = np.random.default_rng(0).choice(gated.samples.shape[0], 16, replace=False)
