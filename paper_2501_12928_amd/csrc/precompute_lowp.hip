@@ -275,22 +275,62 @@ __device__ inline f4 prod6(const bf8 (&x)[3], const bf8 (&y)[3], f4 acc) {
     return acc;
 }
 
+// One workgroup per 64 x 64 tile; per step of 32 rows the workgroup copies
+// both 64-column panels (six planes each, 48 KiB) from HBM into LDS once,
+// and every wave reads its operands there (each wave needs its own 16
+// columns of the row panel and all 64 of the column panel, so reading them
+// straight from memory fetched the column panel four times). Two LDS
+// buffers: the next step's panels are read into registers while this
+// step's are multiplied, and stored after it.
+constexpr int BF_COL = 40;                           // LDS stride of a column: 32 rows + 8 pad (bf16)
+constexpr int BF_PANEL = 6 * 64 * BF_COL;            // one panel, six planes
+constexpr int BF_LOADS = 2 * 6 * 64 * 4 / 256;       // 16-byte reads per thread per step (12)
+
 __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *__restrict__ P,
                                                           int64_t m_pad, int64_t n_pad, int64_t n,
                                                           double2 *__restrict__ Ap) {
+    __shared__ __align__(16) unsigned short lds[2][2 * BF_PANEL];
     int64_t ti, tj;
     tile_of(blockIdx.x, ti, tj);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
     const int64_t plane = n_pad * m_pad;
-    // B operand (a = W[s][64 ti + 16 w + l16]), A operands (b = W[s][64 tj + 16 cb + l16])
-    const unsigned short *pa = P + (TS * ti + 16 * w + l16) * m_pad + 8 * q;
-    const unsigned short *pb = P + (TS * tj + l16) * m_pad + 8 * q;
+    // the thread's share of a step: 16 bytes (8 rows) of one column of one
+    // plane of one panel; e = ((panel * 6 + p) * 64 + col) * 4 + 8-row group
+    const unsigned short *src[BF_LOADS];
+    int dst[BF_LOADS];
+#pragma unroll
+    for (int u = 0; u < BF_LOADS; ++u) {
+        const int e = tid + 256 * u;
+        const int g8 = e & 3, col = (e >> 2) & 63, pp = e >> 8;  // pp = panel * 6 + plane
+        const int panel = pp / 6, p = pp % 6;
+        const int64_t gcol = TS * (panel == 0 ? ti : tj) + col;
+        src[u] = P + (int64_t)p * plane + gcol * m_pad + 8 * g8;
+        dst[u] = panel * BF_PANEL + (p * 64 + col) * BF_COL + 8 * g8;
+    }
+    s8v pre[BF_LOADS];
+    auto fetch = [&](int64_t s0) {
+#pragma unroll
+        for (int u = 0; u < BF_LOADS; ++u) pre[u] = *reinterpret_cast<const s8v *>(src[u] + s0);
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < BF_LOADS; ++u) *reinterpret_cast<s8v *>(&lds[b][dst[u]]) = pre[u];
+    };
+    // B operand a = W[s][64 ti + 16 w + l16] (panel 0), A operands b = W[s][64 tj + 16 cb + l16] (panel 1)
+    auto opnd = [&](int b, int panel, int p, int col) {
+        return __builtin_bit_cast(bf8, *reinterpret_cast<const s8v *>(
+                                           &lds[b][panel * BF_PANEL + (p * 64 + col) * BF_COL + 8 * q]));
+    };
     double sR[4][4], sI[4][4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) sR[cb][r] = sI[cb][r] = 0.0;
 
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
     for (int64_t c0 = 0; c0 < m_pad; c0 += CHUNK_ROWS) {
         f4 aR[4], aI[4];
 #pragma unroll
@@ -299,11 +339,13 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
             aI[cb] = f4{0, 0, 0, 0};
         }
         for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 32) {
+            const bool more = s0 + 32 < m_pad;
+            if (more) fetch(s0 + 32);
             bf8 ar[3], ai[3], nai[3];
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
-                ar[t] = ld_bf8(pa + t * plane + s0);
-                ai[t] = ld_bf8(pa + (3 + t) * plane + s0);
+                ar[t] = opnd(buf, 0, t, 16 * w + l16);
+                ai[t] = opnd(buf, 0, 3 + t, 16 * w + l16);
                 nai[t] = neg_bf8(ai[t]);
             }
 #pragma unroll
@@ -311,8 +353,8 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
                 bf8 br[3], bi[3];
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
-                    br[t] = ld_bf8(pb + 16 * cb * m_pad + t * plane + s0);
-                    bi[t] = ld_bf8(pb + 16 * cb * m_pad + (3 + t) * plane + s0);
+                    br[t] = opnd(buf, 1, t, 16 * cb + l16);
+                    bi[t] = opnd(buf, 1, 3 + t, 16 * cb + l16);
                 }
                 // re: br ar + bi ai;  im: bi ar - br ai
                 aR[cb] = prod6(br, ar, aR[cb]);
@@ -320,6 +362,9 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
                 aI[cb] = prod6(bi, ar, aI[cb]);
                 aI[cb] = prod6(br, nai, aI[cb]);
             }
+            if (more) stash(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
         }
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
