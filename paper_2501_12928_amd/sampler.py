@@ -65,12 +65,15 @@ class Result:
         var = w @ (self.samples - mean) ** 2
         return mean, np.sqrt(var)
 
-    def power_summary(self, theta_true=None):
+    def power_summary(self, theta_true=None, k=None):
         """Per k-bin power P_b = 10^theta_b recovered from the weighted
         samples (theta is log10 power per bin): posterior mean and standard
         deviation of P_b, the median and 16-84% interval of theta_b, and, given
         the values the data were drawn at, the fractional error of the mean
-        power and the offset of the median in posterior standard deviations."""
+        power and the offset of the median in posterior standard deviations.
+        Given the bins' wavenumbers k_b, also the dimensionless spectrum
+        Delta^2_b = k_b^3 P_b / (2 pi^2) (eq. 2), its posterior mean and
+        standard deviation (and its true value)."""
         w = np.exp(self.logw - self.logw.max())
         w /= w.sum()
         P = 10.0 ** self.samples
@@ -92,6 +95,13 @@ class Result:
             out["power_frac_err"] = ((pm - pt) / pt).tolist()
             half = 0.5 * (np.array(out["theta_hi"]) - np.array(out["theta_lo"]))
             out["theta_offset_sigma"] = ((np.array(out["theta_median"]) - tt) / half).tolist()
+        if k is not None:
+            c = np.asarray(k, dtype=np.float64) ** 3 / (2.0 * math.pi ** 2)
+            out["k"] = np.asarray(k, dtype=np.float64).tolist()
+            out["delta2_mean"] = (c * pm).tolist()
+            out["delta2_std"] = (c * ps).tolist()
+            if theta_true is not None:
+                out["delta2_true"] = (c * pt).tolist()
         return out
 
 

@@ -232,6 +232,7 @@ class Instrument:
     norm: float
     bin_of: np.ndarray    # int32 (n_eta n_uv,), k-shell of each coefficient, -1 for foreground modes
     n_k: int
+    k_shell: np.ndarray   # float64 (n_k,), mean |(i_x, i_y, j)| of each shell's coefficients (lattice units)
 
     @property
     def m(self) -> int:
@@ -288,9 +289,11 @@ def instrument(seed: int, F: int = 32, n_bl: int = 625, n_side: int = 64, kx: in
     used = np.unique(shell)
     remap = {b: i for i, b in enumerate(used)}
     bin_of = np.array([remap[b] if b >= 0 else -1 for b in bin_of], dtype=np.int32)
+    eor_bins = bin_of[n_fg * n_uv:]
+    k_shell = np.array([kk[eor_bins == b].mean() for b in range(used.size)])
     return Instrument(freq=freq, bl=bl, lm=np.ascontiguousarray(lm), beam=np.ascontiguousarray(beam),
                       uv=uv, Z=np.ascontiguousarray(Z), norm=1.0 / lm.shape[0], bin_of=bin_of,
-                      n_k=int(used.size))
+                      n_k=int(used.size), k_shell=k_shell)
 
 
 def instrument_instance(ins: Instrument, T: np.ndarray, seed: int, n_theta: int, lo: float = -1.0,

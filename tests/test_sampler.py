@@ -61,9 +61,18 @@ def test_gaussian_evidence_and_posterior():
     assert abs(r.information - H_true) < 0.3
     # power recovery: theta ~ N(mu, sigma^2) gives E[10^theta] = 10^mu exp((sigma ln 10)^2 / 2),
     # median mu and 16-84% interval mu +- sigma
-    ps = r.power_summary(theta_true=MU[:d])
+    k = np.array([0.1, 0.2, 0.5, 1.0])
+    ps = r.power_summary(theta_true=MU[:d], k=k)
     expect = 10.0 ** MU[:d] * math.exp((SIG * math.log(10.0)) ** 2 / 2)
     np.testing.assert_allclose(ps["power_mean"], expect, rtol=0.12)
+    # lognormal spread: std[10^theta] = E[10^theta] sqrt(exp((sigma ln 10)^2) - 1); eq. 2 scales
+    # both moments by k^3 / (2 pi^2)
+    sd_expect = expect * math.sqrt(math.exp((SIG * math.log(10.0)) ** 2) - 1.0)
+    np.testing.assert_allclose(ps["power_std"], sd_expect, rtol=0.25)
+    c = k ** 3 / (2 * math.pi ** 2)
+    np.testing.assert_allclose(ps["delta2_mean"], c * expect, rtol=0.12)
+    np.testing.assert_allclose(ps["delta2_std"], c * sd_expect, rtol=0.25)
+    np.testing.assert_allclose(ps["delta2_true"], c * 10.0 ** MU[:d], rtol=1e-12)
     np.testing.assert_allclose(ps["theta_median"], MU[:d], atol=0.06)
     np.testing.assert_allclose(np.array(ps["theta_hi"]) - np.array(ps["theta_lo"]), 2 * SIG, rtol=0.12)
     assert np.all(np.abs(ps["theta_offset_sigma"]) < 0.15)
