@@ -58,6 +58,33 @@ def test_loss_and_gradient_match_oracle(H, nb):
     s.close()
 
 
+@pytest.mark.parametrize("n_in,M,H,nb", [(64, 1, 4, 1), (1, 2, 8, 17), (13, 3, 128, 16), (5, 2, 132, 33)])
+def test_loss_and_gradient_edge_shapes(n_in, M, H, nb):
+    """Edge shapes of the fused kernels: the widest input (64), one input,
+    hidden widths of 4 (almost all padding), 128 (exactly one 128-unit
+    block) and 132 (just past it), a batch of one sample, batches that end
+    on and just past a 16-sample block, and a single member."""
+    rng = np.random.default_rng(n_in * 100 + H)
+    s = _sur(n_in, M, H)
+    p32 = _params(rng, M, n_in, H).astype(np.float32)
+    x = rng.uniform(-1, 1, size=(M, nb, n_in)).astype(np.float32)
+    y = rng.standard_normal((M, nb)).astype(np.float32)
+    s.set_params(p32)
+    print(f"gpu: surrogate loss/grad n_in={n_in} M={M} H={H} nb={nb}", flush=True)
+    loss, grad = s.loss_grad(x, y)
+    loss = loss.cpu().numpy()
+    grad = grad.cpu().numpy()
+    for z in range(M):
+        l_ref, g_ref = mlp.loss_and_grad(p32[z].astype(np.float64), x[z].astype(np.float64),
+                                         y[z].astype(np.float64), n_in, H)
+        assert abs(loss[z] - l_ref) <= 1e-5 * abs(l_ref) + 1e-7
+        for blk in mlp.unpack(np.arange(g_ref.size), n_in, H):
+            ix = np.asarray(blk).ravel()
+            err = np.linalg.norm(grad[z][ix] - g_ref[ix])
+            assert err <= 1e-4 * np.linalg.norm(g_ref[ix]) + 1e-7, (z, ix[:2], err)
+    s.close()
+
+
 def test_adam_step_matches_oracle():
     import paper_2501_12928_amd as eor
     rng = np.random.default_rng(4)
@@ -83,21 +110,25 @@ def test_adam_step_matches_oracle():
     s.close()
 
 
-def test_inference_matches_oracle_ensemble():
+@pytest.mark.parametrize("n_in,H,B", [(12, 256, 70001), (64, 132, 70001), (12, 256, (1 << 20) + 4097)])
+def test_inference_matches_oracle_ensemble(n_in, H, B):
+    """Member outputs against the oracle on sampled points, and the ensemble
+    statistics against the members' outputs on every point; the last case
+    spans two launches of 2^20 points."""
     import torch
-    rng = np.random.default_rng(5)
-    n_in, M, H = 12, 5, 256
+    rng = np.random.default_rng(5 + H)
+    M = 5
     s = _sur(n_in, M, H)
     p32 = _params(rng, M, n_in, H).astype(np.float32)
     s.set_params(p32)
     s.standardisation(np.array([-1.5e4, 250.0]))
-    th = rng.uniform(-1, 3, size=(70001, n_in))   # more than one inference chunk
-    print("gpu: surrogate inference 70001 points", flush=True)
+    th = rng.uniform(-1, 3, size=(B, n_in))
+    print(f"gpu: surrogate inference {B} points n_in={n_in} H={H}", flush=True)
     mean, spread, mem = s.infer(torch.from_numpy(th).cuda(), members=True)
     mean = mean.cpu().numpy()
     spread = spread.cpu().numpy()
     mem = mem.cpu().numpy()
-    idx = rng.choice(th.shape[0], 2000, replace=False)
+    idx = np.unique(np.concatenate([rng.choice(B, 2000, replace=False), np.arange(B - 64, B)]))
     rm, rs = mlp.ensemble([p.astype(np.float64) for p in p32], th[idx], -1.0, 3.0, -1.5e4, 250.0, n_in, H)
     # FP32 network outputs: |error| of a member output ~ 1e-6 relative to its scale
     assert np.max(np.abs(mean[idx] - rm)) <= 250.0 * 1e-4
