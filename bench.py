@@ -378,6 +378,58 @@ def bench_instrument(args):
     ctx.close()
 
 
+def bench_ooc(args):
+    """Out-of-core likelihood at 20000 x 4096 (12 bins): A exported to host
+    memory, then eor_loglike_host with the device limited to a window of
+    `--ooc-mib` MiB, for the first `--ooc-theta` theta of the metric batch.
+    Reports evals/s, the host<->device bytes per theta of the left-looking
+    schedule and the algorithmic FP64 rate, beside the in-core batch."""
+    import torch
+    import synth
+    import paper_2501_12928_amd as eor
+    inst = synth.gen(CONFIG_ID)
+    n = inst.n
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale)
+    A, dbar, c, K0 = ctx.export_precompute()
+    torch.cuda.synchronize()
+    A = A.cpu().numpy()
+    dbar = dbar.cpu().numpy()
+    th = inst.theta[:args.ooc_theta]
+    # in-core reference timing on the same theta
+    thd = torch.from_numpy(np.ascontiguousarray(th)).cuda()
+    Lin, infin = ctx.loglike_batch(thd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.loglike_batch(thd, out=Lin, info=infin)
+    torch.cuda.synchronize()
+    t_in = time.perf_counter() - t0
+    Lin = Lin.cpu().numpy()
+    ctx.close()
+    budget = args.ooc_mib << 20
+    eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th[:1], budget)
+    t0 = time.perf_counter()
+    L, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th, budget)
+    t_ooc = time.perf_counter() - t0
+    N = (n + 63) // 64
+    tile = 64 * 64 * 16
+    moved = (n * (n + 64) // 2) * 16 + sum((N - j) * j for j in range(N)) * tile + N * (N + 1) // 2 * tile
+    B = th.shape[0]
+    print(json.dumps({
+        "metric": "out-of-core logL evals/s at n=4096 complex FP64 (report)",
+        "value": B / t_ooc, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"T complex128 {inst.m}x{n}, {inst.n_k} k-bins; A in host memory, device window "
+                               f"{args.ooc_mib} MiB; {B} theta one at a time"},
+        "seconds_per_theta": t_ooc / B, "host_device_bytes_per_theta": moved,
+        "host_device_gbs": moved * B / t_ooc / 1e9,
+        "tflops": B * flops_per_theta(n) / t_ooc / 1e12,
+        "in_core_evals_per_s": B / t_in,
+        "info_nonzero": int((info != 0).sum()),
+        "max_rel_diff_vs_in_core": float(np.max(np.abs(L - Lin) / np.abs(Lin)))}))
+
+
 def surrogate_flops(n_in: int, H: int):
     """(inference, training) FP32 flop per sample and member of an
     n_in -> H -> H -> 1 network: the forward pass is its three dense layers;
@@ -475,12 +527,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
-    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress", "surrogate", "instrument"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "group", "gated", "stress", "surrogate", "instrument", "ooc"], default="metric",
                     help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances; "
                          "gated: nested sampling at 20000x4096 without and with the surrogate gate; "
                          "stress: reduced precision on ill-conditioned instruments at 8000x2048; "
                          "surrogate: ensemble training on 1e5 samples and gating of 1e6 proposals; "
-                         "instrument: T from the forward model, then precompute and one batch")
+                         "instrument: T from the forward model, then precompute and one batch; "
+                         "ooc: the likelihood with A in host memory through a small device window")
     ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
     ap.add_argument("--n-live", type=int, default=500)
     ap.add_argument("--first-train", type=int, default=30000)
@@ -495,6 +548,8 @@ def main():
     ap.add_argument("--pool-factor", type=int, default=1)
     ap.add_argument("--instrument-sample", action="store_true",
                     help="instrument workload: also run nested sampling and report the recovered spectrum")
+    ap.add_argument("--ooc-mib", type=int, default=256, help="ooc workload: device window in MiB")
+    ap.add_argument("--ooc-theta", type=int, default=8, help="ooc workload: theta evaluated")
     ap.add_argument("--surrogate-train", type=int, default=100000)
     ap.add_argument("--surrogate-proposals", type=int, default=1000000)
     ap.add_argument("--surrogate-epochs", type=int, default=50)
@@ -535,6 +590,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "instrument":
         return bench_instrument(args)
+    if args.workload == "ooc":
+        return bench_ooc(args)
 
     inst = synth.gen(CONFIG_ID)
     B, n, m = inst.theta.shape[0], inst.n, inst.m

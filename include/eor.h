@@ -320,6 +320,35 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
                             double *rows_out, int32_t *index_out, int32_t *count_out, void *stream);
 
 /*
+ * Out-of-core likelihood, for Sigma too large for the device (the case of the
+ * paper's MAGMA footnote, running BayesEoR with matrices beyond the GPU's
+ * memory): the same logL as eor_loglike_batch, one theta at a time, with A in
+ * host memory and the factor L kept in a pinned host buffer of the library,
+ * while the device holds one column of 64 x 64 tiles and a window of earlier
+ * columns (left-looking blocked Cholesky, FP64 MFMA tile products).
+ *   A        host complex128 [n x ldA] row-major, Hermitian; only the lower
+ *            triangle is read (eor_export_precompute writes it)
+ *   dbar     host complex128 [n];  c, K0: the scalars eor_export_precompute
+ *            returns (K0 = -m ln pi - sum ln sigma^2)
+ *   n_k, bin_of [n], fixed_var [n], bin_scale [n_k] (or NULL = 1): host, as
+ *            for eor_precompute
+ *   theta    host double [B x n_k];  logL host double [B];  info host int32
+ *            [B] or NULL (0, -1 for an invalid theta, or the 1-based column of
+ *            the first non-positive pivot; logL = -inf then)
+ *   device_bytes: the device memory the call may use; at least one column of
+ *            tiles twice over (about 2 ceil(n/64) x 64 KiB) plus O(n)
+ * Synchronous; allocates its device buffers and a pinned host factor of
+ * ceil(n/64) (ceil(n/64) + 1) / 2 tiles, and frees them before returning.
+ * Errors: EOR_ERR_ARG (sizes, NULL arrays, bin_of out of range, fixed
+ * variance not positive), EOR_ERR_OOM (device_bytes too small, allocation),
+ * EOR_ERR_HIP.
+ */
+eor_status eor_loglike_host(int device, int64_t n, const double *A, int64_t ldA, const double *dbar,
+                            double c, double K0, int32_t n_k, const int32_t *bin_of,
+                            const double *fixed_var, const double *bin_scale, int64_t B,
+                            const double *theta, size_t device_bytes, double *logL, int32_t *info);
+
+/*
  * Instrument forward model (the step before the likelihood, from the
  * instrument model of the paper's "Running BayesEoR" section: a primary-beam
  * response and the uv sampling of the data). The paper names the inputs but

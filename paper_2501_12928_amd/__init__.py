@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.eor_compact_rows.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P]
         L.eor_probe_fp64_mfma.argtypes = [ctypes.c_int, _I64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
+        L.eor_loglike_host.argtypes = [ctypes.c_int, _I64, _P, _I64, _P, ctypes.c_double, ctypes.c_double, _I32,
+                                       _P, _P, _P, _I64, _P, ctypes.c_size_t, _P, _P]
         L.eor_forward_model.argtypes = [_I64, _I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, ctypes.c_double,
                                         _P, _I64, _P]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
@@ -105,7 +107,7 @@ def lib() -> ctypes.CDLL:
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
                      "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
-                     "eor_compact_rows", "eor_probe_fp64_mfma", "eor_forward_model"):
+                     "eor_compact_rows", "eor_probe_fp64_mfma", "eor_forward_model", "eor_loglike_host"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -400,6 +402,28 @@ def compact_rows(keep, rows=None):
                                  None if out is None else out.data_ptr(), idx.data_ptr(), cnt.data_ptr(), _stream()))
     c = int(cnt.item())
     return (None if out is None else out[:c]), idx[:c], c
+
+
+def loglike_host(A, dbar, c, K0, n_k, bin_of, fixed_var, bin_scale, theta, device_bytes, device=0):
+    """(logL [B], info [B]) of eor_loglike_host: A (complex128 [n, n], host,
+    lower triangle read) and the rest in host memory; the device uses at most
+    `device_bytes` (Sigma factored out of core, one theta at a time)."""
+    A = np.asarray(A, dtype=np.complex128)
+    if not A.flags.c_contiguous:
+        A = np.ascontiguousarray(A)
+    dbar = np.ascontiguousarray(dbar, dtype=np.complex128)
+    bin_of = np.ascontiguousarray(bin_of, dtype=np.int32)
+    fixed_var = np.ascontiguousarray(fixed_var, dtype=np.float64)
+    bs = None if bin_scale is None else np.ascontiguousarray(bin_scale, dtype=np.float64)
+    theta = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+    n, B = A.shape[0], theta.shape[0]
+    logL = np.empty(B)
+    info = np.empty(B, dtype=np.int32)
+    check(lib().eor_loglike_host(int(device), n, A.ctypes.data, A.shape[1], dbar.ctypes.data, float(c), float(K0),
+                                 int(n_k), bin_of.ctypes.data, fixed_var.ctypes.data,
+                                 None if bs is None else bs.ctypes.data, B, theta.ctypes.data, int(device_bytes),
+                                 logL.ctypes.data, info.ctypes.data))
+    return logL, info
 
 
 def forward_model(freq, bl, lm, beam, uv, Z, norm, out=None):

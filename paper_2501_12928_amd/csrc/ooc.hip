@@ -1,0 +1,429 @@
+// Likelihood with Sigma factored through a bounded device window: the
+// out-of-core case (the paper's MAGMA footnote: matrices larger than the
+// GPU's memory). A stays in the caller's host memory, the factor L of the
+// current theta in a pinned host buffer of the library, and the device holds
+// one column of 64 x 64 tiles plus a window of earlier columns of L.
+//
+// Left-looking blocked Cholesky, one tile column j at a time:
+//   C_i = A_ij + [i == j] Phi^-1                       (i >= j, copied in)
+//   C_i -= sum_{k < j} L_ik L_jk^H                      (windows of earlier columns)
+//   L_jj = chol(C_j), Linv = L_jj^-1, y_j = Linv w_j    (one workgroup)
+//   L_ij = C_i Linv^H,  w_i -= L_ij y_j                 (i > j)
+// with w = dbar at the start, then logL = K0 - ln det Phi - 2 sum ln L_dd -
+// (c - |y|^2), the same combination as the batched path. Tiles are row-major
+// 64 x 64 complex. On the host, A (copied once per call from the caller's
+// row-major matrix) and L are packed by tile columns in pinned memory: tile
+// (i, k), i >= k, at k N - k (k - 1) / 2 + (i - k), so that the part of a
+// tile column below any row is one contiguous block and every transfer of
+// the schedule is a single DMA. The tile products run on FP64 MFMA with
+// three real products per complex step.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace eor {
+
+namespace {
+
+constexpr int OT = 64;
+constexpr int OT2 = OT * OT;
+
+__device__ inline d4 mfma64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct OocState {
+    double logdet;    // 2 sum ln L_dd
+    double quad;      // |y|^2
+    double lndetphi;  // ln det Phi
+    int32_t info;     // 0, -1 (invalid theta), or the 1-based failing column
+};
+
+__global__ void ooc_reset_kernel(OocState *st) {
+    st->logdet = 0.0;
+    st->quad = 0.0;
+    st->lndetphi = 0.0;
+    st->info = 0;
+}
+
+// Diagonal tile of column j: add 1/phi_d to the diagonal (d < n), set the
+// padding's diagonal to 1, and add the column's ln phi_d to ln det Phi in
+// a fixed order.
+__global__ __launch_bounds__(64) void ooc_diag_kernel(double2 *__restrict__ C0, int64_t j, int64_t n,
+                                                     const double *__restrict__ theta,
+                                                     const int32_t *__restrict__ bin_of,
+                                                     const double *__restrict__ fixed_var,
+                                                     const double *__restrict__ bin_scale, OocState *st) {
+    __shared__ double lp[OT];
+    __shared__ int bad[OT];
+    const int t = threadIdx.x;
+    const int64_t d = OT * j + t;
+    double l = 0.0;
+    int b_ = 0;
+    if (d < n) {
+        const int b = bin_of[d];
+        const double phi = b >= 0 ? bin_scale[b] * exp10(theta[b]) : fixed_var[d];
+        if (!(phi > 0.0) || !isfinite(phi)) b_ = 1;
+        else {
+            C0[t * OT + t].x += 1.0 / phi;
+            l = log(phi);
+        }
+    } else {
+        C0[t * OT + t] = make_double2(1.0, 0.0);
+    }
+    lp[t] = l;
+    bad[t] = b_;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        int anybad = 0;
+        for (int e = 0; e < OT; ++e) {
+            s += lp[e];
+            anybad |= bad[e];
+        }
+        if (anybad && st->info == 0) st->info = -1;
+        st->lndetphi += s;
+    }
+}
+
+// out[r][c] (+|-)= sum_s X[r][s] conj(Y[c][s]) for one 64 x 64 tile pair:
+// four waves, wave w rows 16w..16w+15, four 16-column blocks; returns the
+// accumulators T1 = xr yr, T2 = xi yi, T3 = (xr + xi)(yr - yi), so that
+// re = T1 + T2 and im = T3 - T1 + T2.
+__device__ inline void tile_xyh(const double2 *__restrict__ X, const double2 *__restrict__ Y, int w, int l16,
+                                int q, d4 t1[4], d4 t2[4], d4 t3[4]) {
+#pragma unroll 4
+    for (int s0 = 0; s0 < OT; s0 += 4) {
+        const double2 xv = X[(16 * w + l16) * OT + s0 + q];
+        const double xs = xv.x + xv.y;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const double2 yv = Y[(16 * cb + l16) * OT + s0 + q];
+            t1[cb] = mfma64(xv.x, yv.x, t1[cb]);
+            t2[cb] = mfma64(xv.y, yv.y, t2[cb]);
+            t3[cb] = mfma64(xs, yv.x - yv.y, t3[cb]);
+        }
+    }
+}
+
+// C_t -= sum_k Lw[k][t] Lw[k][0]^H for t = blockIdx.x (window column k holds
+// rows j .. N-1 of an earlier tile column, `rows` tiles; row 0 is row j).
+__global__ __launch_bounds__(256) void ooc_update_kernel(double2 *__restrict__ C, const double2 *__restrict__ Lw,
+                                                         int W, int64_t rows, const OocState *st) {
+    if (st->info != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    const int64_t t = blockIdx.x;
+    d4 t1[4], t2[4], t3[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) t1[cb] = t2[cb] = t3[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < W; ++k)
+        tile_xyh(Lw + ((int64_t)k * rows + t) * OT2, Lw + (int64_t)k * rows * OT2, w, l16, q, t1, t2, t3);
+    // lane holds [16 w + q + 4 r][16 cb + l16]
+    double2 *Ct = C + t * OT2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + q + 4 * r;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            double2 &e = Ct[row * OT + 16 * cb + l16];
+            const double re = t1[cb][r] + t2[cb][r], im = t3[cb][r] - t1[cb][r] + t2[cb][r];
+            e = make_double2(e.x - re, e.y - im);
+        }
+    }
+}
+
+// Diagonal tile of column j: Cholesky in LDS, ln det, the inverse of L_jj
+// and y_j = L_jj^-1 w_j. One workgroup.
+__global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0, double2 *__restrict__ Linv,
+                                                        double2 *__restrict__ w, double2 *__restrict__ y,
+                                                        int64_t j, OocState *st) {
+    __shared__ double2 S[OT][OT + 1];
+    __shared__ double2 V[OT][OT + 1];
+    __shared__ int fail_col;
+    if (st->info != 0) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < OT2; e += 256) {
+        S[e / OT][e % OT] = C0[e];
+        V[e / OT][e % OT] = make_double2(0.0, 0.0);
+    }
+    if (tid == 0) fail_col = 0;
+    __syncthreads();
+    for (int c = 0; c < OT; ++c) {
+        const double dcc = S[c][c].x;
+        if (!(dcc > 0.0) || !isfinite(dcc)) {
+            if (tid == 0) fail_col = c + 1;
+            break;  // uniform: every thread reads the same value
+        }
+        const double lc = sqrt(dcc);
+        __syncthreads();
+        // column c of L below the diagonal
+        for (int r = c + 1 + tid; r < OT; r += 256) S[r][c] = make_double2(S[r][c].x / lc, S[r][c].y / lc);
+        __syncthreads();
+        if (tid == 0) S[c][c] = make_double2(lc, 0.0);
+        // trailing update of the lower triangle: S[r][s] -= L[r][c] conj(L[s][c]), c < s <= r
+        const int m = OT - 1 - c;
+        for (int e = tid; e < m * m; e += 256) {
+            const int r = c + 1 + e / m, s = c + 1 + e % m;
+            if (s <= r) {
+                const double2 a = S[r][c], b = S[s][c];
+                S[r][s] = make_double2(S[r][s].x - (a.x * b.x + a.y * b.y), S[r][s].y - (a.y * b.x - a.x * b.y));
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (fail_col != 0) {
+        if (tid == 0) st->info = (int32_t)(OT * j + fail_col);
+        return;
+    }
+    // inverse of the lower factor, one column per thread
+    if (tid < OT) {
+        const int cc = tid;
+        V[cc][cc] = make_double2(1.0 / S[cc][cc].x, 0.0);
+        for (int r = cc + 1; r < OT; ++r) {
+            double sr = 0.0, si = 0.0;
+            for (int t = cc; t < r; ++t) {
+                const double2 a = S[r][t], b = V[t][cc];
+                sr += a.x * b.x - a.y * b.y;
+                si += a.x * b.y + a.y * b.x;
+            }
+            const double inv = -1.0 / S[r][r].x;
+            V[r][cc] = make_double2(sr * inv, si * inv);
+        }
+    }
+    __syncthreads();
+    // write L_jj (zero above the diagonal) and its inverse
+    for (int e = tid; e < OT2; e += 256) {
+        const int r = e / OT, c = e % OT;
+        C0[e] = c <= r ? S[r][c] : make_double2(0.0, 0.0);
+        Linv[e] = c <= r ? V[r][c] : make_double2(0.0, 0.0);
+    }
+    // y_j = Linv w_j
+    __shared__ double2 yj[OT];
+    if (tid < OT) {
+        double sr = 0.0, si = 0.0;
+        for (int t = 0; t <= tid; ++t) {
+            const double2 a = V[tid][t], b = w[OT * j + t];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+        }
+        yj[tid] = make_double2(sr, si);
+        y[OT * j + tid] = yj[tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double ld = 0.0, qd = 0.0;
+        for (int d = 0; d < OT; ++d) {
+            ld += log(S[d][d].x);
+            qd += yj[d].x * yj[d].x + yj[d].y * yj[d].y;
+        }
+        st->logdet += 2.0 * ld;
+        st->quad += qd;
+    }
+}
+
+// L_ij = C_i Linv^H for the tiles below the diagonal (t = blockIdx.x + 1),
+// then w_i -= L_ij y_j.
+__global__ __launch_bounds__(256) void ooc_trsm_kernel(double2 *__restrict__ C, const double2 *__restrict__ Linv,
+                                                       double2 *__restrict__ w, const double2 *__restrict__ y,
+                                                       int64_t j, const OocState *st) {
+    if (st->info != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    const int64_t t = (int64_t)blockIdx.x + 1;
+    double2 *Ct = C + t * OT2;
+    d4 t1[4], t2[4], t3[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) t1[cb] = t2[cb] = t3[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    tile_xyh(Ct, Linv, wv, l16, q, t1, t2, t3);
+    // each wave reads and writes only its own 16 rows of C_t
+    const double2 *yj = y + OT * j;
+    double pr[4] = {0.0, 0.0, 0.0, 0.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wv + q + 4 * r;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const double re = t1[cb][r] + t2[cb][r], im = t3[cb][r] - t1[cb][r] + t2[cb][r];
+            Ct[row * OT + 16 * cb + l16] = make_double2(re, im);
+            const double2 b = yj[16 * cb + l16];
+            pr[r] += re * b.x - im * b.y;
+            pi[r] += re * b.y + im * b.x;
+        }
+    }
+    // sum over the 16 columns of a lane group, fixed xor tree
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            pr[r] += __shfl_xor(pr[r], o);
+            pi[r] += __shfl_xor(pi[r], o);
+        }
+    }
+    if (l16 == 0) {
+        const int64_t i = j + t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double2 &e = w[OT * i + 16 * wv + q + 4 * r];
+            e = make_double2(e.x - pr[r], e.y - pi[r]);
+        }
+    }
+}
+
+__global__ void ooc_finish_kernel(const OocState *st, double K0, double c, double *logL, int32_t *info) {
+    if (st->info != 0) {
+        *logL = -INFINITY;
+        *info = st->info;
+    } else {
+        *logL = K0 - st->lndetphi - st->logdet - (c - st->quad);
+        *info = 0;
+    }
+}
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+}  // namespace eor
+
+extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, int64_t ldA,
+                                       const double *dbar, double c, double K0, int32_t n_k,
+                                       const int32_t *bin_of, const double *fixed_var, const double *bin_scale,
+                                       int64_t B, const double *theta, size_t device_bytes, double *logL,
+                                       int32_t *info) {
+    using namespace eor;
+    if (n < 1 || n_k < 1 || B < 0 || ldA < n || !A || !dbar || !bin_of || !fixed_var || !theta || !logL)
+        return fail_status(EOR_ERR_ARG, "eor_loglike_host: bad sizes or NULL array");
+    if (n > ((int64_t)1 << 22)) return fail_status(EOR_ERR_ARG, "eor_loglike_host: n > 2^22");
+    for (int64_t d = 0; d < n; ++d) {
+        if (bin_of[d] >= n_k || bin_of[d] < -1) return fail_status(EOR_ERR_ARG, "eor_loglike_host: bin_of out of range");
+        if (bin_of[d] < 0 && !(fixed_var[d] > 0.0 && std::isfinite(fixed_var[d])))
+            return fail_status(EOR_ERR_ARG, "eor_loglike_host: fixed variance must be positive and finite");
+    }
+    if (B == 0) return EOR_OK;
+    const int64_t N = (n + OT - 1) / OT, n_pad = N * OT;
+    const size_t tile_b = (size_t)OT2 * sizeof(double2);
+    // device: column C (N tiles) + Linv (1) + window (cap tiles) + vectors and tables
+    const size_t fixed_b = (size_t)(N + 1) * tile_b + 2 * (size_t)n_pad * sizeof(double2) +
+                           (size_t)n * (sizeof(int32_t) + sizeof(double)) + 4096;
+    if (device_bytes < fixed_b + (size_t)N * tile_b)
+        return fail_status(EOR_ERR_OOM, "eor_loglike_host: device_bytes below one column of tiles and its window");
+    const int64_t cap = (int64_t)((device_bytes - fixed_b) / tile_b);
+
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_status(e, "eor_loglike_host: device");
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_status(e, "eor_loglike_host: stream");
+    DevBuf<double2> C, Lw, Linv, w, y, dbar_d;
+    DevBuf<int32_t> bin_d;
+    DevBuf<double> fix_d, scale_d, theta_d, out_d;
+    DevBuf<int32_t> info_d;
+    DevBuf<OocState> st;
+    double2 *Lh = nullptr;  // pinned host factor, tile columns packed
+    double2 *Ah = nullptr;  // pinned host copy of A, same packing
+    auto done = [&](eor_status r) {
+        if (s) (void)hipStreamDestroy(s);
+        if (Lh) (void)hipHostFree(Lh);
+        if (Ah) (void)hipHostFree(Ah);
+        if (prev >= 0) (void)hipSetDevice(prev);
+        return r;
+    };
+    const int64_t ntile = N * (N + 1) / 2;
+    auto col_off = [&](int64_t k) { return k * N - k * (k - 1) / 2; };  // first tile of tile column k
+    e = hipMalloc(&C.p, (size_t)N * tile_b);
+    if (e == hipSuccess) e = hipMalloc(&Lw.p, (size_t)cap * tile_b);
+    if (e == hipSuccess) e = hipMalloc(&Linv.p, tile_b);
+    if (e == hipSuccess) e = hipMalloc(&w.p, n_pad * sizeof(double2));
+    if (e == hipSuccess) e = hipMalloc(&y.p, n_pad * sizeof(double2));
+    if (e == hipSuccess) e = hipMalloc(&dbar_d.p, n_pad * sizeof(double2));
+    if (e == hipSuccess) e = hipMalloc(&bin_d.p, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&fix_d.p, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&scale_d.p, n_k * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&theta_d.p, (size_t)B * n_k * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&out_d.p, (size_t)B * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&info_d.p, (size_t)B * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&st.p, sizeof(OocState));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&Lh, (size_t)ntile * tile_b, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&Ah, (size_t)ntile * tile_b, 0);
+    if (e != hipSuccess) return done(hip_status(e, "eor_loglike_host: allocation"));
+    // A's lower tiles, zero-padded past n, into the packed host copy
+    const double2 *Asrc = reinterpret_cast<const double2 *>(A);
+    for (int64_t k = 0; k < N; ++k)
+        for (int64_t i = k; i < N; ++i) {
+            double2 *tile = Ah + (col_off(k) + (i - k)) * OT2;
+            for (int r = 0; r < OT; ++r) {
+                const int64_t gr = OT * i + r;
+                double2 *dst = tile + r * OT;
+                const int64_t cols = std::min<int64_t>(OT, n - OT * k);
+                if (gr < n) {
+                    std::copy(Asrc + gr * ldA + OT * k, Asrc + gr * ldA + OT * k + cols, dst);
+                    std::fill(dst + cols, dst + OT, make_double2(0.0, 0.0));
+                } else {
+                    std::fill(dst, dst + OT, make_double2(0.0, 0.0));
+                }
+            }
+        }
+    std::vector<double> scale_h(n_k, 1.0);
+    if (bin_scale) std::copy(bin_scale, bin_scale + n_k, scale_h.begin());
+    e = hipMemsetAsync(dbar_d.p, 0, n_pad * sizeof(double2), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dbar_d.p, dbar, n * sizeof(double2), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(bin_d.p, bin_of, n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(fix_d.p, fixed_var, n * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(scale_d.p, scale_h.data(), n_k * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(theta_d.p, theta, (size_t)B * n_k * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(hip_status(e, "eor_loglike_host: inputs"));
+
+    for (int64_t b = 0; b < B; ++b) {
+        hipLaunchKernelGGL(ooc_reset_kernel, dim3(1), dim3(1), 0, s, st.p);
+        e = hipMemcpyAsync(w.p, dbar_d.p, n_pad * sizeof(double2), hipMemcpyDeviceToDevice, s);
+        for (int64_t j = 0; e == hipSuccess && j < N; ++j) {
+            const int64_t rows = N - j;
+            // tile column j of A (rows j .. N-1): one contiguous block
+            e = hipMemcpyAsync(C.p, Ah + col_off(j) * OT2, (size_t)rows * tile_b, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL(ooc_diag_kernel, dim3(1), dim3(OT), 0, s, C.p, j, n, theta_d.p + b * n_k, bin_d.p,
+                               fix_d.p, scale_d.p, st.p);
+            // earlier tile columns, rows j .. N-1, in windows of W columns
+            const int64_t W = std::max<int64_t>(1, std::min<int64_t>(j, cap / rows));
+            for (int64_t k0 = 0; k0 < j; k0 += W) {
+                const int64_t wk = std::min<int64_t>(W, j - k0);
+                for (int64_t k = 0; k < wk && e == hipSuccess; ++k) {
+                    const int64_t kk = k0 + k;
+                    e = hipMemcpyAsync(Lw.p + k * rows * OT2, Lh + (col_off(kk) + (j - kk)) * OT2,
+                                       (size_t)rows * tile_b, hipMemcpyHostToDevice, s);
+                }
+                if (e != hipSuccess) break;
+                hipLaunchKernelGGL(ooc_update_kernel, dim3((unsigned)rows), dim3(256), 0, s, C.p, Lw.p, (int)wk, rows,
+                                   st.p);
+            }
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, C.p, Linv.p, w.p, y.p, j, st.p);
+            if (rows > 1)
+                hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, C.p, Linv.p, w.p,
+                                   y.p, j, st.p);
+            // tile column j of L to the host factor: one contiguous block
+            e = hipMemcpyAsync(Lh + col_off(j) * OT2, C.p, (size_t)rows * tile_b, hipMemcpyDeviceToHost, s);
+        }
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(ooc_finish_kernel, dim3(1), dim3(1), 0, s, st.p, K0, c, out_d.p + b, info_d.p + b);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(logL, out_d.p, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && info)
+        e = hipMemcpyAsync(info, info_d.p, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(hip_status(e, "eor_loglike_host"));
+    return done(EOR_OK);
+}

@@ -52,6 +52,20 @@ def test_argument_errors_without_gpu():
     assert L.eor_forward_model(1, 1, 1, 2, 2, p, p, p, p, p, p, 1.0, p, 3, None) == eor.EOR_ERR_ARG
     assert L.eor_forward_model(1, 1, 1, 1, 1, p, None, p, p, p, p, 1.0, p, 1, None) == eor.EOR_ERR_ARG
     assert L.eor_forward_model(1, 1, 1, 1, 1, p, p, p, p, p, p, float("inf"), p, 1, None) == eor.EOR_ERR_ARG
+    # out-of-core likelihood: sizes, bin map, fixed variances and the device budget are checked first
+    A = np.zeros((4, 4), dtype=np.complex128)
+    db = np.zeros(4, dtype=np.complex128)
+    bins = np.array([0, 0, 1, -1], dtype=np.int32)
+    fv = np.array([0.0, 0.0, 0.0, 1e4])
+    th = np.zeros((1, 2))
+    out = np.zeros(1)
+    inf_ = np.zeros(1, dtype=np.int32)
+    args = lambda n, b, f, nb: (0, n, A.ctypes.data, 4, db.ctypes.data, 0.0, 0.0, 2, b.ctypes.data, f.ctypes.data,
+                                None, 1, th.ctypes.data, nb, out.ctypes.data, inf_.ctypes.data)
+    assert L.eor_loglike_host(*args(0, bins, fv, 1 << 30)) == eor.EOR_ERR_ARG
+    assert L.eor_loglike_host(*args(4, np.array([0, 2, 1, -1], dtype=np.int32), fv, 1 << 30)) == eor.EOR_ERR_ARG
+    assert L.eor_loglike_host(*args(4, bins, np.zeros(4), 1 << 30)) == eor.EOR_ERR_ARG
+    assert L.eor_loglike_host(*args(4, bins, fv, 1024)) == eor.EOR_ERR_OOM
 
 
 def test_product_package_does_not_reference_oracle():

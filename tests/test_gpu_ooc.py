@@ -1,0 +1,84 @@
+"""Out-of-core likelihood (eor_loglike_host): A in host memory, the factor in
+a pinned host buffer, the device holding a column of tiles and a window of
+earlier columns. Checked against the FP64 oracle: on the oracle's own A at
+a ragged size with the smallest device window and with a roomy one, at the
+full 20000 x 4096 size against the stored oracle values, and on the failure
+paths (invalid theta, a pivot that is not positive)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import have_gpu, tol
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="no GPU")]
+
+TILE_BYTES = 64 * 64 * 16
+
+
+def _min_budget(n):
+    N = (n + 63) // 64
+    return (2 * N + 2) * TILE_BYTES
+
+
+@pytest.mark.parametrize("budget", ["min", "roomy"])
+def test_ooc_matches_oracle_on_its_own_A(orc, budget):
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=71, m=900, n=333, n_k=4, n_theta=12)
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    ref, rinfo = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, inst.theta)
+    assert np.all(rinfo == 0)
+    nbytes = _min_budget(inst.n) if budget == "min" else 1 << 30
+    print(f"gpu: out-of-core logL n=333 budget={nbytes}", flush=True)
+    got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
+                                 inst.theta, nbytes)
+    assert np.all(info == 0)
+    assert np.all(np.abs(got - ref) <= tol(ref))
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
+
+
+def test_ooc_full_size_against_stored_oracle_values():
+    """20000 x 4096, 12 bins: the GPU precompute, A exported to host memory,
+    then the out-of-core factorisation through a 256 MiB device window, for
+    the sampled theta whose oracle values are stored."""
+    import torch
+    import paper_2501_12928_amd as eor
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_oracle_sample.json")))
+    inst = synth.gen(3)
+    assert inst.digest() == g["digest"]
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale)
+    A, dbar, c, K0 = ctx.export_precompute()
+    torch.cuda.synchronize()
+    A = A.cpu().numpy()
+    dbar = dbar.cpu().numpy()
+    ctx.close()
+    idx = np.asarray(g["index"])
+    print("gpu: out-of-core logL n=4096, 8 theta, 256 MiB window", flush=True)
+    got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
+                                 inst.theta[idx], 256 << 20)
+    ref = np.asarray(g["logL"])
+    assert np.all(info == 0)
+    assert np.all(np.abs(got - ref) <= tol(ref))
+
+
+def test_ooc_failure_paths(orc):
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=72, m=400, n=130, n_k=3, n_theta=3)
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    th = inst.theta.copy()
+    th[1, 2] = np.nan
+    print("gpu: out-of-core failure paths n=130", flush=True)
+    got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, None, th, 1 << 28)
+    assert info[1] == -1 and got[1] == -np.inf
+    assert info[0] == 0 and info[2] == 0 and np.all(np.isfinite(got[[0, 2]]))
+    # an A whose 70th diagonal entry is far below minus the prior precision: the first
+    # non-positive pivot is column 70 (1-based 70), in the second tile
+    A2 = A.copy()
+    A2[69, 69] = -1e12
+    got2, info2 = eor.loglike_host(A2, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, None, inst.theta[:1],
+                                   1 << 28)
+    assert info2[0] == 70 and got2[0] == -np.inf
