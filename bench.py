@@ -412,9 +412,14 @@ def bench_ooc(args):
     t0 = time.perf_counter()
     L, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th, budget)
     t_ooc = time.perf_counter() - t0
+    # bytes of the library's schedule: passes of J tile columns (half the window's tiles / N),
+    # A and L once each, and every earlier column's rows below a pass once per pass
     N = (n + 63) // 64
     tile = 64 * 64 * 16
-    moved = (n * (n + 64) // 2) * 16 + sum((N - j) * j for j in range(N)) * tile + N * (N + 1) // 2 * tile
+    fixed = tile + 2 * N * 64 * 16 + n * 12 + 4096
+    avail = (budget - fixed) // tile
+    J = max(1, min(N, (avail // 2) // N))
+    moved = 2 * (N * (N + 1) // 2) * tile + sum(j0 * (N - j0) for j0 in range(0, N, J)) * tile
     B = th.shape[0]
     print(json.dumps({
         "metric": "out-of-core logL evals/s at n=4096 complex FP64 (report)",
@@ -422,7 +427,7 @@ def bench_ooc(args):
         "data": "synthetic",
         "config": {"workload": f"T complex128 {inst.m}x{n}, {inst.n_k} k-bins; A in host memory, device window "
                                f"{args.ooc_mib} MiB; {B} theta one at a time"},
-        "seconds_per_theta": t_ooc / B, "host_device_bytes_per_theta": moved,
+        "seconds_per_theta": t_ooc / B, "host_device_bytes_per_theta": moved, "columns_per_pass": J,
         "host_device_gbs": moved * B / t_ooc / 1e9,
         "tflops": B * flops_per_theta(n) / t_ooc / 1e12,
         "in_core_evals_per_s": B / t_in,

@@ -4,11 +4,15 @@
 // current theta in a pinned host buffer of the library, and the device holds
 // one column of 64 x 64 tiles plus a window of earlier columns of L.
 //
-// Left-looking blocked Cholesky, one tile column j at a time:
-//   C_i = A_ij + [i == j] Phi^-1                       (i >= j, copied in)
-//   C_i -= sum_{k < j} L_ik L_jk^H                      (windows of earlier columns)
-//   L_jj = chol(C_j), Linv = L_jj^-1, y_j = Linv w_j    (one workgroup)
-//   L_ij = C_i Linv^H,  w_i -= L_ij y_j                 (i > j)
+// Left-looking blocked Cholesky over passes of J tile columns [j0, j1)
+// (as many as half the device window holds):
+//   C_ij = A_ij + [i == j] Phi^-1                    (i >= j, the pass copied in)
+//   C_ij -= sum_{k < j0} L_ik L_jk^H                  (windows of earlier columns,
+//                                                     each read once per pass)
+// then for j = j0 .. j1-1:
+//   C_ij -= sum_{j0 <= k < j} L_ik L_jk^H             (columns of this pass)
+//   L_jj = chol(C_jj), Linv = L_jj^-1, y_j = Linv w_j (one workgroup)
+//   L_ij = C_ij Linv^H,  w_i -= L_ij y_j              (i > j)
 // with w = dbar at the start, then logL = K0 - ln det Phi - 2 sum ln L_dd -
 // (c - |y|^2), the same combination as the batched path. Tiles are row-major
 // 64 x 64 complex. On the host, A (copied once per call from the caller's
@@ -108,20 +112,9 @@ __device__ inline void tile_xyh(const double2 *__restrict__ X, const double2 *__
     }
 }
 
-// C_t -= sum_k Lw[k][t] Lw[k][0]^H for t = blockIdx.x (window column k holds
-// rows j .. N-1 of an earlier tile column, `rows` tiles; row 0 is row j).
-__global__ __launch_bounds__(256) void ooc_update_kernel(double2 *__restrict__ C, const double2 *__restrict__ Lw,
-                                                         int W, int64_t rows, const OocState *st) {
-    if (st->info != 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-    const int64_t t = blockIdx.x;
-    d4 t1[4], t2[4], t3[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) t1[cb] = t2[cb] = t3[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < W; ++k)
-        tile_xyh(Lw + ((int64_t)k * rows + t) * OT2, Lw + (int64_t)k * rows * OT2, w, l16, q, t1, t2, t3);
+__device__ inline void tile_sub(double2 *__restrict__ Ct, int w, int l16, int q, const d4 t1[4], const d4 t2[4],
+                                const d4 t3[4]) {
     // lane holds [16 w + q + 4 r][16 cb + l16]
-    double2 *Ct = C + t * OT2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = 16 * w + q + 4 * r;
@@ -132,6 +125,46 @@ __global__ __launch_bounds__(256) void ooc_update_kernel(double2 *__restrict__ C
             e = make_double2(e.x - re, e.y - im);
         }
     }
+}
+
+// Super-column [j0, j1) on the device, packed by tile columns (column j's
+// tiles, rows j .. N-1, from local tile col_off(j) - col_off(j0)). One
+// workgroup per tile (i, j): C_ij -= sum_k L_ik L_jk^H over the window of
+// earlier columns, window column k holding rows j0 .. N-1 (N - j0 tiles).
+__global__ __launch_bounds__(256) void ooc_window_kernel(double2 *__restrict__ C, const double2 *__restrict__ Lw,
+                                                         int W, int64_t j0, int64_t j1, int64_t N,
+                                                         const OocState *st) {
+    if (st->info != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    int64_t b = blockIdx.x, j = j0;
+    while (j < j1 - 1 && b >= N - j) {
+        b -= N - j;
+        ++j;
+    }
+    const int64_t i = j + b, rows = N - j0;
+    d4 t1[4], t2[4], t3[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) t1[cb] = t2[cb] = t3[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < W; ++k)
+        tile_xyh(Lw + ((int64_t)k * rows + (i - j0)) * OT2, Lw + ((int64_t)k * rows + (j - j0)) * OT2, w, l16, q,
+                 t1, t2, t3);
+    tile_sub(C + (int64_t)blockIdx.x * OT2, w, l16, q, t1, t2, t3);
+}
+
+// Column j of the super-column: C_ij -= sum_{k = j0}^{j-1} L_ik L_jk^H with
+// the factored columns k still on the device (i = j + blockIdx.x).
+__global__ __launch_bounds__(256) void ooc_inner_kernel(double2 *__restrict__ C, int64_t j, int64_t j0, int64_t N,
+                                                        const OocState *st) {
+    if (st->info != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
+    const int64_t i = j + blockIdx.x;
+    auto loc = [&](int64_t k) { return (k - j0) * N - ((k * (k - 1)) / 2 - (j0 * (j0 - 1)) / 2); };
+    d4 t1[4], t2[4], t3[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) t1[cb] = t2[cb] = t3[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = j0; k < j; ++k)
+        tile_xyh(C + (loc(k) + (i - k)) * OT2, C + (loc(k) + (j - k)) * OT2, w, l16, q, t1, t2, t3);
+    tile_sub(C + (loc(j) + (i - j)) * OT2, w, l16, q, t1, t2, t3);
 }
 
 // Diagonal tile of column j: Cholesky in LDS, ln det, the inverse of L_jj
@@ -310,13 +343,15 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
     if (B == 0) return EOR_OK;
     const int64_t N = (n + OT - 1) / OT, n_pad = N * OT;
     const size_t tile_b = (size_t)OT2 * sizeof(double2);
-    // device: column C (N tiles) + Linv (1) + window (cap tiles) + vectors and tables
-    const size_t fixed_b = (size_t)(N + 1) * tile_b + 2 * (size_t)n_pad * sizeof(double2) +
-                           (size_t)n * (sizeof(int32_t) + sizeof(double)) + 4096;
-    if (device_bytes < fixed_b + (size_t)N * tile_b)
-        return fail_status(EOR_ERR_OOM, "eor_loglike_host: device_bytes below one column of tiles and its window");
-    const int64_t cap = (int64_t)((device_bytes - fixed_b) / tile_b);
-
+    // device: Linv (1 tile), vectors and tables, then tiles shared between the
+    // super-column (capC) and the window of earlier columns (capW)
+    const size_t fixed_b = tile_b + 2 * (size_t)n_pad * sizeof(double2) + (size_t)n * (sizeof(int32_t) + sizeof(double)) +
+                           4096;
+    if (device_bytes < fixed_b + 2 * (size_t)N * tile_b)
+        return fail_status(EOR_ERR_OOM, "eor_loglike_host: device_bytes below two columns of tiles");
+    const int64_t avail = (int64_t)((device_bytes - fixed_b) / tile_b);
+    const int64_t J = std::max<int64_t>(1, std::min<int64_t>(N, (avail / 2) / N));  // tile columns per pass
+    const int64_t capC = J * N, cap = avail - capC;                                  // cap >= N
     int prev = -1;
     (void)hipGetDevice(&prev);
     hipError_t e = hipSetDevice(device);
@@ -340,7 +375,7 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
     };
     const int64_t ntile = N * (N + 1) / 2;
     auto col_off = [&](int64_t k) { return k * N - k * (k - 1) / 2; };  // first tile of tile column k
-    e = hipMalloc(&C.p, (size_t)N * tile_b);
+    e = hipMalloc(&C.p, (size_t)capC * tile_b);
     if (e == hipSuccess) e = hipMalloc(&Lw.p, (size_t)cap * tile_b);
     if (e == hipSuccess) e = hipMalloc(&Linv.p, tile_b);
     if (e == hipSuccess) e = hipMalloc(&w.p, n_pad * sizeof(double2));
@@ -388,33 +423,41 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
     for (int64_t b = 0; b < B; ++b) {
         hipLaunchKernelGGL(ooc_reset_kernel, dim3(1), dim3(1), 0, s, st.p);
         e = hipMemcpyAsync(w.p, dbar_d.p, n_pad * sizeof(double2), hipMemcpyDeviceToDevice, s);
-        for (int64_t j = 0; e == hipSuccess && j < N; ++j) {
-            const int64_t rows = N - j;
-            // tile column j of A (rows j .. N-1): one contiguous block
-            e = hipMemcpyAsync(C.p, Ah + col_off(j) * OT2, (size_t)rows * tile_b, hipMemcpyHostToDevice, s);
+        for (int64_t j0 = 0; e == hipSuccess && j0 < N; j0 += J) {
+            const int64_t j1 = std::min<int64_t>(N, j0 + J), nt = col_off(j1) - col_off(j0), rows0 = N - j0;
+            // tile columns j0 .. j1-1 of A: one contiguous block
+            e = hipMemcpyAsync(C.p, Ah + col_off(j0) * OT2, (size_t)nt * tile_b, hipMemcpyHostToDevice, s);
             if (e != hipSuccess) break;
-            hipLaunchKernelGGL(ooc_diag_kernel, dim3(1), dim3(OT), 0, s, C.p, j, n, theta_d.p + b * n_k, bin_d.p,
-                               fix_d.p, scale_d.p, st.p);
-            // earlier tile columns, rows j .. N-1, in windows of W columns
-            const int64_t W = std::max<int64_t>(1, std::min<int64_t>(j, cap / rows));
-            for (int64_t k0 = 0; k0 < j; k0 += W) {
-                const int64_t wk = std::min<int64_t>(W, j - k0);
+            for (int64_t j = j0; j < j1; ++j)
+                hipLaunchKernelGGL(ooc_diag_kernel, dim3(1), dim3(OT), 0, s, C.p + (col_off(j) - col_off(j0)) * OT2,
+                                   j, n, theta_d.p + b * n_k, bin_d.p, fix_d.p, scale_d.p, st.p);
+            // earlier tile columns, rows j0 .. N-1, in windows of W columns, each read once per pass
+            const int64_t W = std::max<int64_t>(1, std::min<int64_t>(j0, cap / rows0));
+            for (int64_t k0 = 0; k0 < j0; k0 += W) {
+                const int64_t wk = std::min<int64_t>(W, j0 - k0);
                 for (int64_t k = 0; k < wk && e == hipSuccess; ++k) {
                     const int64_t kk = k0 + k;
-                    e = hipMemcpyAsync(Lw.p + k * rows * OT2, Lh + (col_off(kk) + (j - kk)) * OT2,
-                                       (size_t)rows * tile_b, hipMemcpyHostToDevice, s);
+                    e = hipMemcpyAsync(Lw.p + k * rows0 * OT2, Lh + (col_off(kk) + (j0 - kk)) * OT2,
+                                       (size_t)rows0 * tile_b, hipMemcpyHostToDevice, s);
                 }
                 if (e != hipSuccess) break;
-                hipLaunchKernelGGL(ooc_update_kernel, dim3((unsigned)rows), dim3(256), 0, s, C.p, Lw.p, (int)wk, rows,
+                hipLaunchKernelGGL(ooc_window_kernel, dim3((unsigned)nt), dim3(256), 0, s, C.p, Lw.p, (int)wk, j0, j1, N,
                                    st.p);
             }
             if (e != hipSuccess) break;
-            hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, C.p, Linv.p, w.p, y.p, j, st.p);
-            if (rows > 1)
-                hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, C.p, Linv.p, w.p,
-                                   y.p, j, st.p);
-            // tile column j of L to the host factor: one contiguous block
-            e = hipMemcpyAsync(Lh + col_off(j) * OT2, C.p, (size_t)rows * tile_b, hipMemcpyDeviceToHost, s);
+            // the pass's own columns, left to right
+            for (int64_t j = j0; j < j1; ++j) {
+                const int64_t rows = N - j;
+                double2 *Cj = C.p + (col_off(j) - col_off(j0)) * OT2;
+                if (j > j0)
+                    hipLaunchKernelGGL(ooc_inner_kernel, dim3((unsigned)rows), dim3(256), 0, s, C.p, j, j0, N, st.p);
+                hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, Cj, Linv.p, w.p, y.p, j, st.p);
+                if (rows > 1)
+                    hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, Cj, Linv.p, w.p,
+                                       y.p, j, st.p);
+            }
+            // tile columns j0 .. j1-1 of L to the host factor: one contiguous block
+            e = hipMemcpyAsync(Lh + col_off(j0) * OT2, C.p, (size_t)nt * tile_b, hipMemcpyDeviceToHost, s);
         }
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(ooc_finish_kernel, dim3(1), dim3(1), 0, s, st.p, K0, c, out_d.p + b, info_d.p + b);
