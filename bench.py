@@ -51,15 +51,16 @@ def kernel_digest() -> str:
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per likelihood launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def counters_per_launch():
+    """(HBM bytes, FP64 MFMA instructions) per likelihood launch from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source; else (None, None)."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, None
     t = json.load(open(TRAFFIC_FILE))
     if t.get("kernel_sha") != kernel_digest():
-        return None
-    return t.get("bytes_per_launch")
+        return None, None
+    return t.get("bytes_per_launch"), t.get("mfma_instructions")
 
 
 def cpu_baseline(inst, n_rows: int = 2000):
@@ -639,7 +640,11 @@ def main():
     fl = B * flops_per_theta(n)
     achieved = fl / (like_ms / 1e3) / 1e12
     like_ms_median = float(np.median([a.elapsed_time(b) for a, b in events]))
-    traffic = traffic_per_launch()
+    traffic, mfma_insts = counters_per_launch()
+    # flops the matrix cores execute (16x16x4 FP64 MFMA = 2048 flops each): with
+    # three real products per complex step they are about 3/4 of the LAPACK count,
+    # so `frac` (LAPACK count) can pass 1 while the executed fraction cannot
+    executed = None if mfma_insts is None else mfma_insts * 2048.0 / (like_ms / 1e3) / 1e12
     # measured FP64 matrix peak over a run about as long as one likelihood
     # launch (a round is 8 MFMAs of 64 cycles for each of the two waves that
     # share a SIMD: 1024 cycles)
@@ -666,7 +671,12 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "likelihood_kernel", "launch_ms": like_ms, "launch_ms_median": like_ms_median,
-                     "flops_per_launch": fl, "peak_measured": peak_meas,
+                     "flops_per_launch": fl, "flops_basis": "LAPACK complex count, 8 real flops per complex "
+                                                            "multiply-add; the kernel runs 3 real MFMA "
+                                                            "products per complex step",
+                     "executed_tflops": executed,
+                     "executed_frac": None if executed is None else executed / PEAK_FP64_TFLOPS,
+                     "peak_measured": peak_meas,
                      "frac_measured": achieved / peak_meas, "peak_measured_run_ms": probe_ms},
         "loglike_evals_per_s": B / (like_ms / 1e3),
         "tuning": dict(zip(("stages", "wg_per_cu", "tiles_per_pass"), ctx.tuning())),
