@@ -2,7 +2,7 @@
 // networks n_in -> H -> H -> 1 with GELU after each hidden layer, in FP32,
 // trained on exact evaluations by these kernels (forward, hand-derived
 // backward, Adam) and used to gate sampler proposals, with the exact FP64
-// likelihood as the fallback and as the judge of every accepted point.
+// likelihood as the fallback and as the arbiter of every accepted point.
 //
 // Layout per member (flat FP32, row-major matrices):
 //   W1 [H x n_in], b1 [H], W2 [H x H], b2 [H], W3 [H], b3 [1]
