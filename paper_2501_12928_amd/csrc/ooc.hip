@@ -168,12 +168,16 @@ __global__ __launch_bounds__(256) void ooc_inner_kernel(double2 *__restrict__ C,
 }
 
 // Diagonal tile of column j: Cholesky in LDS, ln det, the inverse of L_jj
-// and y_j = L_jj^-1 w_j. One workgroup.
+// and y_j = L_jj^-1 w_j. One workgroup. The elimination runs unscaled,
+// S[r][s] -= S[r][c] conj(S[s][c]) / d_c with d_c = S[c][c] (one barrier per
+// column), and L[r][c] = S[r][c] / sqrt(d_c) is formed where it is used.
 __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0, double2 *__restrict__ Linv,
                                                         double2 *__restrict__ w, double2 *__restrict__ y,
                                                         int64_t j, OocState *st) {
     __shared__ double2 S[OT][OT + 1];
     __shared__ double2 V[OT][OT + 1];
+    __shared__ double sq[OT];
+    __shared__ double2 yj[OT];
     __shared__ int fail_col;
     if (st->info != 0) return;
     const int tid = threadIdx.x;
@@ -189,19 +193,14 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
             if (tid == 0) fail_col = c + 1;
             break;  // uniform: every thread reads the same value
         }
-        const double lc = sqrt(dcc);
-        __syncthreads();
-        // column c of L below the diagonal
-        for (int r = c + 1 + tid; r < OT; r += 256) S[r][c] = make_double2(S[r][c].x / lc, S[r][c].y / lc);
-        __syncthreads();
-        if (tid == 0) S[c][c] = make_double2(lc, 0.0);
-        // trailing update of the lower triangle: S[r][s] -= L[r][c] conj(L[s][c]), c < s <= r
+        const double inv = 1.0 / dcc;
         const int m = OT - 1 - c;
         for (int e = tid; e < m * m; e += 256) {
             const int r = c + 1 + e / m, s = c + 1 + e % m;
             if (s <= r) {
                 const double2 a = S[r][c], b = S[s][c];
-                S[r][s] = make_double2(S[r][s].x - (a.x * b.x + a.y * b.y), S[r][s].y - (a.y * b.x - a.x * b.y));
+                S[r][s] = make_double2(S[r][s].x - (a.x * b.x + a.y * b.y) * inv,
+                                       S[r][s].y - (a.y * b.x - a.x * b.y) * inv);
             }
         }
         __syncthreads();
@@ -211,30 +210,45 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
         if (tid == 0) st->info = (int32_t)(OT * j + fail_col);
         return;
     }
-    // inverse of the lower factor, one column per thread
-    if (tid < OT) {
-        const int cc = tid;
-        V[cc][cc] = make_double2(1.0 / S[cc][cc].x, 0.0);
-        for (int r = cc + 1; r < OT; ++r) {
-            double sr = 0.0, si = 0.0;
-            for (int t = cc; t < r; ++t) {
-                const double2 a = S[r][t], b = V[t][cc];
-                sr += a.x * b.x - a.y * b.y;
-                si += a.x * b.y + a.y * b.x;
+    if (tid < OT) sq[tid] = sqrt(S[tid][tid].x);
+    __syncthreads();
+    // inverse of the lower factor: four lanes per column (one wave holds
+    // sixteen columns), the sum over t split by t mod 4 and added in a fixed
+    // xor order; lane 0 of the four writes V[r][cc], which the wave's later
+    // LDS reads see in order
+    {
+        const int cc = tid >> 2, part = tid & 3;
+        if (part == 0) V[cc][cc] = make_double2(1.0 / sq[cc], 0.0);
+        for (int r = 1; r < OT; ++r) {
+            if (r > cc) {
+                double sr = 0.0, si = 0.0;
+                for (int t = cc + part; t < r; t += 4) {
+                    const double2 a = S[r][t], b = V[t][cc];
+                    const double lt = 1.0 / sq[t];
+                    sr += (a.x * b.x - a.y * b.y) * lt;
+                    si += (a.x * b.y + a.y * b.x) * lt;
+                }
+                sr += __shfl_xor(sr, 1);
+                si += __shfl_xor(si, 1);
+                sr += __shfl_xor(sr, 2);
+                si += __shfl_xor(si, 2);
+                if (part == 0) {
+                    const double f = -1.0 / sq[r];
+                    V[r][cc] = make_double2(sr * f, si * f);
+                }
             }
-            const double inv = -1.0 / S[r][r].x;
-            V[r][cc] = make_double2(sr * inv, si * inv);
         }
     }
     __syncthreads();
     // write L_jj (zero above the diagonal) and its inverse
     for (int e = tid; e < OT2; e += 256) {
         const int r = e / OT, c = e % OT;
-        C0[e] = c <= r ? S[r][c] : make_double2(0.0, 0.0);
+        const double2 l = c < r ? make_double2(S[r][c].x / sq[c], S[r][c].y / sq[c])
+                                : (c == r ? make_double2(sq[r], 0.0) : make_double2(0.0, 0.0));
+        C0[e] = l;
         Linv[e] = c <= r ? V[r][c] : make_double2(0.0, 0.0);
     }
     // y_j = Linv w_j
-    __shared__ double2 yj[OT];
     if (tid < OT) {
         double sr = 0.0, si = 0.0;
         for (int t = 0; t <= tid; ++t) {
@@ -249,7 +263,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     if (tid == 0) {
         double ld = 0.0, qd = 0.0;
         for (int d = 0; d < OT; ++d) {
-            ld += log(S[d][d].x);
+            ld += log(sq[d]);
             qd += yj[d].x * yj[d].x + yj[d].y * yj[d].y;
         }
         st->logdet += 2.0 * ld;
