@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
                                                         int64_t j, OocState *st) {
     __shared__ double2 S[OT][OT + 1];
     __shared__ double2 V[OT][OT + 1];
-    __shared__ double sq[OT];
+    __shared__ double sq[OT], isq[OT];
     __shared__ double2 yj[OT];
     __shared__ int fail_col;
     if (st->info != 0) return;
@@ -210,7 +210,10 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
         if (tid == 0) st->info = (int32_t)(OT * j + fail_col);
         return;
     }
-    if (tid < OT) sq[tid] = sqrt(S[tid][tid].x);
+    if (tid < OT) {
+        sq[tid] = sqrt(S[tid][tid].x);
+        isq[tid] = 1.0 / sq[tid];
+    }
     __syncthreads();
     // inverse of the lower factor: four lanes per column (one wave holds
     // sixteen columns), the sum over t split by t mod 4 and added in a fixed
@@ -218,13 +221,13 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     // LDS reads see in order
     {
         const int cc = tid >> 2, part = tid & 3;
-        if (part == 0) V[cc][cc] = make_double2(1.0 / sq[cc], 0.0);
+        if (part == 0) V[cc][cc] = make_double2(isq[cc], 0.0);
         for (int r = 1; r < OT; ++r) {
             if (r > cc) {
                 double sr = 0.0, si = 0.0;
                 for (int t = cc + part; t < r; t += 4) {
                     const double2 a = S[r][t], b = V[t][cc];
-                    const double lt = 1.0 / sq[t];
+                    const double lt = isq[t];
                     sr += (a.x * b.x - a.y * b.y) * lt;
                     si += (a.x * b.y + a.y * b.x) * lt;
                 }
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
                 sr += __shfl_xor(sr, 2);
                 si += __shfl_xor(si, 2);
                 if (part == 0) {
-                    const double f = -1.0 / sq[r];
+                    const double f = -isq[r];
                     V[r][cc] = make_double2(sr * f, si * f);
                 }
             }
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     // write L_jj (zero above the diagonal) and its inverse
     for (int e = tid; e < OT2; e += 256) {
         const int r = e / OT, c = e % OT;
-        const double2 l = c < r ? make_double2(S[r][c].x / sq[c], S[r][c].y / sq[c])
+        const double2 l = c < r ? make_double2(S[r][c].x * isq[c], S[r][c].y * isq[c])
                                 : (c == r ? make_double2(sq[r], 0.0) : make_double2(0.0, 0.0));
         C0[e] = l;
         Linv[e] = c <= r ? V[r][c] : make_double2(0.0, 0.0);
