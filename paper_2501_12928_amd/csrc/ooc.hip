@@ -10,9 +10,9 @@
 //   C_ij -= sum_{k < j0} L_ik L_jk^H                  (windows of earlier columns,
 //                                                     each read once per pass)
 // then for j = j0 .. j1-1:
-//   C_ij -= sum_{j0 <= k < j} L_ik L_jk^H             (columns of this pass)
 //   L_jj = chol(C_jj), Linv = L_jj^-1, y_j = Linv w_j (one workgroup)
 //   L_ij = C_ij Linv^H,  w_i -= L_ij y_j              (i > j)
+//   C_il -= L_ij L_lj^H                                (the pass's later columns l)
 // with w = dbar at the start, then logL = K0 - ln det Phi - 2 sum ln L_dd -
 // (c - |y|^2), the same combination as the batched path. Tiles are row-major
 // 64 x 64 complex. On the host, A (copied once per call from the caller's
@@ -151,19 +151,24 @@ __global__ __launch_bounds__(256) void ooc_window_kernel(double2 *__restrict__ C
     tile_sub(C + (int64_t)blockIdx.x * OT2, w, l16, q, t1, t2, t3);
 }
 
-// Column j of the super-column: C_ij -= sum_{k = j0}^{j-1} L_ik L_jk^H with
-// the factored columns k still on the device (i = j + blockIdx.x).
-__global__ __launch_bounds__(256) void ooc_inner_kernel(double2 *__restrict__ C, int64_t j, int64_t j0, int64_t N,
-                                                        const OocState *st) {
+// After column k of a pass is factored: C_ij -= L_ik L_jk^H for every later
+// column j < j1 of the pass and i >= j, one workgroup per tile (the tiles of
+// columns k+1 .. j1-1 are one contiguous run of the pass's packing).
+__global__ __launch_bounds__(256) void ooc_pass_kernel(double2 *__restrict__ C, int64_t k, int64_t j0, int64_t j1,
+                                                       int64_t N, const OocState *st) {
     if (st->info != 0) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
-    const int64_t i = j + blockIdx.x;
-    auto loc = [&](int64_t k) { return (k - j0) * N - ((k * (k - 1)) / 2 - (j0 * (j0 - 1)) / 2); };
+    auto loc = [&](int64_t c) { return (c - j0) * N - ((c * (c - 1)) / 2 - (j0 * (j0 - 1)) / 2); };
+    int64_t b = blockIdx.x, j = k + 1;
+    while (j < j1 - 1 && b >= N - j) {
+        b -= N - j;
+        ++j;
+    }
+    const int64_t i = j + b;
     d4 t1[4], t2[4], t3[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) t1[cb] = t2[cb] = t3[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t k = j0; k < j; ++k)
-        tile_xyh(C + (loc(k) + (i - k)) * OT2, C + (loc(k) + (j - k)) * OT2, w, l16, q, t1, t2, t3);
+    tile_xyh(C + (loc(k) + (i - k)) * OT2, C + (loc(k) + (j - k)) * OT2, w, l16, q, t1, t2, t3);
     tile_sub(C + (loc(j) + (i - j)) * OT2, w, l16, q, t1, t2, t3);
 }
 
@@ -462,16 +467,18 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
                                    st.p);
             }
             if (e != hipSuccess) break;
-            // the pass's own columns, left to right
+            // the pass's own columns, left to right; each finished column updates
+            // the later columns of the pass at once
             for (int64_t j = j0; j < j1; ++j) {
                 const int64_t rows = N - j;
                 double2 *Cj = C.p + (col_off(j) - col_off(j0)) * OT2;
-                if (j > j0)
-                    hipLaunchKernelGGL(ooc_inner_kernel, dim3((unsigned)rows), dim3(256), 0, s, C.p, j, j0, N, st.p);
                 hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, Cj, Linv.p, w.p, y.p, j, st.p);
                 if (rows > 1)
                     hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, Cj, Linv.p, w.p,
                                        y.p, j, st.p);
+                if (j + 1 < j1)
+                    hipLaunchKernelGGL(ooc_pass_kernel, dim3((unsigned)(col_off(j1) - col_off(j + 1))), dim3(256), 0,
+                                       s, C.p, j, j0, j1, N, st.p);
             }
             // tile columns j0 .. j1-1 of L to the host factor: one contiguous block
             e = hipMemcpyAsync(Lh + col_off(j0) * OT2, C.p, (size_t)nt * tile_b, hipMemcpyDeviceToHost, s);

@@ -1,6 +1,7 @@
 """CPU model of the out-of-core schedule of eor_loglike_host (host loop of
 csrc/ooc.hip): the same packing of tile columns, pass width, window sizes
-and workgroup-to-tile mapping, on small tiles in numpy. It checks that every
+and workgroup-to-tile mappings (window and within-pass updates), on small
+tiles in numpy. It checks that every
 index stays inside the buffers the library allocates and that the schedule
 computes the Cholesky factor (against numpy), for windows from the smallest
 allowed to roomy ones and for ragged tile counts."""
@@ -52,15 +53,20 @@ def _schedule(n, avail, bs=4, seed=0):
         loc = lambda k: (k - j0) * N - ((k * (k - 1)) // 2 - (j0 * (j0 - 1)) // 2)
         for j in range(j0, j1):
             assert loc(j) == col_off(j) - col_off(j0)
-            if j > j0:
-                for i in range(j, N):
-                    C[loc(j) + i - j] = C[loc(j) + i - j] - sum(C[loc(k) + i - k] @ C[loc(k) + j - k].conj().T
-                                                                for k in range(j0, j))
             Ljj = np.linalg.cholesky(C[loc(j)])
             C[loc(j)] = Ljj
             Linv = np.linalg.inv(Ljj)
             for t in range(1, N - j):
                 C[loc(j) + t] = C[loc(j) + t] @ Linv.conj().T
+            if j + 1 < j1:  # workgroup -> tile (i, l) as ooc_pass_kernel maps it
+                for blk in range(col_off(j1) - col_off(j + 1)):
+                    b, l = blk, j + 1
+                    while l < j1 - 1 and b >= N - l:
+                        b -= N - l
+                        l += 1
+                    i = l + b
+                    assert i < N and loc(l) + (i - l) == loc(j + 1) + blk
+                    C[loc(l) + i - l] = C[loc(l) + i - l] - C[loc(j) + i - j] @ C[loc(j) + l - j].conj().T
         for t in range(nt):
             Lh[col_off(j0) + t] = C[t]
     L = np.zeros((npad, npad), complex)
