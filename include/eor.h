@@ -324,9 +324,9 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
  * paper's MAGMA footnote, running BayesEoR with matrices beyond the GPU's
  * memory): the same logL as eor_loglike_batch, one theta at a time, with A in
  * host memory and the factor L kept in a pinned host buffer of the library,
- * while the device holds one column of 64 x 64 tiles and a window of earlier
- * columns (blocked Cholesky in passes of tile columns: left-looking across passes,
- * right-looking inside one; FP64 MFMA tile products).
+ * while the device holds a pass of tile columns (64 x 64 tiles) and a window of
+ * earlier columns (blocked Cholesky in passes of tile columns: left-looking across
+ * passes, right-looking inside one; FP64 MFMA tile products).
  *   A        host complex128 [n x ldA] row-major, Hermitian; only the lower
  *            triangle is read (eor_export_precompute writes it)
  *   dbar     host complex128 [n];  c, K0: the scalars eor_export_precompute

@@ -2,14 +2,14 @@
 // out-of-core case (the paper's MAGMA footnote: matrices larger than the
 // GPU's memory). A stays in the caller's host memory, the factor L of the
 // current theta in a pinned host buffer of the library, and the device holds
-// one column of 64 x 64 tiles plus a window of earlier columns of L.
+// a pass of tile columns of 64 x 64 tiles plus a window of earlier columns of L.
 //
-// Left-looking blocked Cholesky over passes of J tile columns [j0, j1)
-// (as many as half the device window holds):
+// Blocked Cholesky over passes of J tile columns [j0, j1) (as many as half
+// the device window holds), left-looking across passes:
 //   C_ij = A_ij + [i == j] Phi^-1                    (i >= j, the pass copied in)
 //   C_ij -= sum_{k < j0} L_ik L_jk^H                  (windows of earlier columns,
 //                                                     each read once per pass)
-// then for j = j0 .. j1-1:
+// then, right-looking inside the pass, for j = j0 .. j1-1:
 //   L_jj = chol(C_jj), Linv = L_jj^-1, y_j = Linv w_j (one workgroup)
 //   L_ij = C_ij Linv^H,  w_i -= L_ij y_j              (i > j)
 //   C_il -= L_ij L_lj^H                                (the pass's later columns l)
