@@ -264,16 +264,10 @@ __device__ inline bf8 neg_bf8(bf8 x) {
     return __builtin_bit_cast(bf8, v);
 }
 
-// x y with x = xh + xm + xl, y = yh + ym + yl: the six leading products.
-__device__ inline f4 prod6(const bf8 (&x)[3], const bf8 (&y)[3], f4 acc) {
-    acc = mfma_bf16(x[2], y[0], acc);
-    acc = mfma_bf16(x[1], y[1], acc);
-    acc = mfma_bf16(x[0], y[2], acc);
-    acc = mfma_bf16(x[1], y[0], acc);
-    acc = mfma_bf16(x[0], y[1], acc);
-    acc = mfma_bf16(x[0], y[0], acc);
-    return acc;
-}
+// x y with x = xh + xm + xl, y = yh + ym + yl: the six leading products,
+// smallest first, term e being x[P6X[e]] y[P6Y[e]].
+constexpr int P6X[6] = {2, 1, 0, 1, 0, 0};
+constexpr int P6Y[6] = {0, 1, 2, 0, 1, 0};
 
 // One workgroup per 64 x 64 tile; per step of 32 rows the workgroup copies
 // both 64-column panels (six planes each, 48 KiB) from HBM into LDS once,
@@ -348,19 +342,34 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
                 ai[t] = opnd(buf, 0, 3 + t, 16 * w + l16);
                 nai[t] = neg_bf8(ai[t]);
             }
+            // re: br ar + bi ai;  im: bi ar - br ai. Two 16-column blocks at a
+            // time, the products of their four accumulators issued in turn so
+            // that no product waits on the one before it; each accumulator
+            // still takes its twelve products in the same order
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                bf8 br[3], bi[3];
+            for (int cp = 0; cp < 4; cp += 2) {
+                bf8 br[2][3], bi[2][3];
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    br[t] = opnd(buf, 1, t, 16 * cb + l16);
-                    bi[t] = opnd(buf, 1, 3 + t, 16 * cb + l16);
-                }
-                // re: br ar + bi ai;  im: bi ar - br ai
-                aR[cb] = prod6(br, ar, aR[cb]);
-                aR[cb] = prod6(bi, ai, aR[cb]);
-                aI[cb] = prod6(bi, ar, aI[cb]);
-                aI[cb] = prod6(br, nai, aI[cb]);
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        br[h][t] = opnd(buf, 1, t, 16 * (cp + h) + l16);
+                        bi[h][t] = opnd(buf, 1, 3 + t, 16 * (cp + h) + l16);
+                    }
+#pragma unroll
+                for (int e = 0; e < 6; ++e)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        aR[cp + h] = mfma_bf16(br[h][P6X[e]], ar[P6Y[e]], aR[cp + h]);
+                        aI[cp + h] = mfma_bf16(bi[h][P6X[e]], ar[P6Y[e]], aI[cp + h]);
+                    }
+#pragma unroll
+                for (int e = 0; e < 6; ++e)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        aR[cp + h] = mfma_bf16(bi[h][P6X[e]], ai[P6Y[e]], aR[cp + h]);
+                        aI[cp + h] = mfma_bf16(br[h][P6X[e]], nai[P6Y[e]], aI[cp + h]);
+                    }
             }
             if (more) stash(buf ^ 1);
             __syncthreads();
