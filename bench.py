@@ -384,9 +384,11 @@ def bench_instrument(args):
 def bench_ooc(args):
     """Out-of-core likelihood at 20000 x 4096 (12 bins): A exported to host
     memory, then eor_loglike_host with the device limited to a window of
-    `--ooc-mib` MiB, for the first `--ooc-theta` theta of the metric batch.
-    Reports evals/s, the host<->device bytes per theta of the left-looking
-    schedule and the algorithmic FP64 rate, beside the in-core batch."""
+    `--ooc-mib` MiB, for the first `--ooc-theta` theta of the metric batch,
+    `--ooc-lanes` at a time (0 = the library's choice). Reports evals/s over
+    the whole call (packing A into pinned memory included), the time of a
+    one-theta call, the library's schedule (lanes, pass width, host<->device
+    bytes per theta) and the algorithmic FP64 rate, beside the in-core batch."""
     import torch
     import synth
     import paper_2501_12928_amd as eor
@@ -411,27 +413,27 @@ def bench_ooc(args):
     Lin = Lin.cpu().numpy()
     ctx.close()
     budget = args.ooc_mib << 20
-    eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th[:1], budget)
+    lanes = args.ooc_lanes
+    plan = eor.loglike_host_plan(n, inst.n_k, budget, lanes)
     t0 = time.perf_counter()
-    L, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th, budget)
+    eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th[:1], budget,
+                     lanes=lanes)
+    t_one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, th, budget,
+                               lanes=lanes)
     t_ooc = time.perf_counter() - t0
-    # bytes of the library's schedule: passes of J tile columns (half the window's tiles / N),
-    # A and L once each, and every earlier column's rows below a pass once per pass
-    N = (n + 63) // 64
-    tile = 64 * 64 * 16
-    fixed = tile + 2 * N * 64 * 16 + n * 12 + 4096
-    avail = (budget - fixed) // tile
-    J = max(1, min(N, (avail // 2) // N))
-    moved = 2 * (N * (N + 1) // 2) * tile + sum(j0 * (N - j0) for j0 in range(0, N, J)) * tile
     B = th.shape[0]
+    moved = plan["link_bytes"]
     print(json.dumps({
         "metric": "out-of-core logL evals/s at n=4096 complex FP64 (report)",
         "value": B / t_ooc, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"T complex128 {inst.m}x{n}, {inst.n_k} k-bins; A in host memory, device window "
-                               f"{args.ooc_mib} MiB; {B} theta one at a time"},
-        "seconds_per_theta": t_ooc / B, "host_device_bytes_per_theta": moved, "columns_per_pass": J,
-        "host_device_gbs": moved * B / t_ooc / 1e9,
+                               f"{args.ooc_mib} MiB; {B} theta, {plan['lanes']} at a time"},
+        "seconds_per_theta": t_ooc / B, "seconds_one_theta_call": t_one,
+        "lanes": plan["lanes"], "columns_per_pass": plan["cols_per_pass"],
+        "host_device_bytes_per_theta": moved, "host_device_gbs": moved * B / t_ooc / 1e9,
         "tflops": B * flops_per_theta(n) / t_ooc / 1e12,
         "in_core_evals_per_s": B / t_in,
         "info_nonzero": int((info != 0).sum()),
@@ -558,6 +560,8 @@ def main():
                     help="instrument workload: also run nested sampling and report the recovered spectrum")
     ap.add_argument("--ooc-mib", type=int, default=256, help="ooc workload: device window in MiB")
     ap.add_argument("--ooc-theta", type=int, default=8, help="ooc workload: theta evaluated")
+    ap.add_argument("--ooc-lanes", type=int, default=0,
+                    help="ooc workload: theta factored at once (0 = the library's choice)")
     ap.add_argument("--surrogate-train", type=int, default=100000)
     ap.add_argument("--surrogate-proposals", type=int, default=1000000)
     ap.add_argument("--surrogate-epochs", type=int, default=50)

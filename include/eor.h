@@ -322,11 +322,13 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
 /*
  * Out-of-core likelihood, for Sigma too large for the device (the case of the
  * paper's MAGMA footnote, running BayesEoR with matrices beyond the GPU's
- * memory): the same logL as eor_loglike_batch, one theta at a time, with A in
- * host memory and the factor L kept in a pinned host buffer of the library,
- * while the device holds a pass of tile columns (64 x 64 tiles) and a window of
- * earlier columns (blocked Cholesky in passes of tile columns: left-looking across
- * passes, right-looking inside one; FP64 MFMA tile products).
+ * memory): the same logL as eor_loglike_batch, with A in host memory and each
+ * theta's factor L kept in a pinned host buffer of the library, while the
+ * device holds a pass of tile columns (64 x 64 tiles) and a window of
+ * earlier columns (blocked Cholesky in passes of tile columns: left-looking
+ * across passes, right-looking inside one; FP64 MFMA tile products).
+ * Up to four theta are factored at once ("lanes"), each on its own stream
+ * with its own share of the device memory and its own pinned host factor.
  *   A        host complex128 [n x ldA] row-major, Hermitian; only the lower
  *            triangle is read (eor_export_precompute writes it)
  *   dbar     host complex128 [n];  c, K0: the scalars eor_export_precompute
@@ -336,18 +338,42 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
  *   theta    host double [B x n_k];  logL host double [B];  info host int32
  *            [B] or NULL (0, -1 for an invalid theta, or the 1-based column of
  *            the first non-positive pivot; logL = -inf then)
- *   device_bytes: the device memory the call may use; at least one column of
- *            tiles twice over (about 2 ceil(n/64) x 64 KiB) plus O(n)
- * Synchronous; allocates its device buffers and a pinned host factor of
- * ceil(n/64) (ceil(n/64) + 1) / 2 tiles, and frees them before returning.
+ *   device_bytes: the device memory the call may use, split evenly between
+ *            the lanes; each lane needs one column of tiles twice over (about
+ *            2 ceil(n/64) x 64 KiB) plus O(n)
+ *   lanes    1..4, or 0: as many (4, 2 or 1) as leave every lane at least
+ *            min(ceil(n/64), 8) tile columns per pass and keep the pinned
+ *            host buffers (lanes + 1 copies of the packed lower triangle)
+ *            within half of the host's physical memory
+ * The schedule (lanes, pass width) follows from n, n_k, device_bytes and
+ * lanes alone, never from B, so a theta's result does not depend on the
+ * batch it is in; a different pass width sums the tile products in a
+ * different order, so results for different device_bytes or lanes agree to
+ * rounding only. Synchronous; allocates its device buffers, a pinned packed
+ * copy of A and one pinned host factor per lane in use (ceil(n/64)
+ * (ceil(n/64) + 1) / 2 tiles each), and frees them before returning.
  * Errors: EOR_ERR_ARG (sizes, NULL arrays, bin_of out of range, fixed
- * variance not positive), EOR_ERR_OOM (device_bytes too small, allocation),
- * EOR_ERR_HIP.
+ * variance not positive, lanes outside 0..4), EOR_ERR_OOM (device_bytes too
+ * small for the lanes, allocation), EOR_ERR_HIP.
  */
 eor_status eor_loglike_host(int device, int64_t n, const double *A, int64_t ldA, const double *dbar,
                             double c, double K0, int32_t n_k, const int32_t *bin_of,
                             const double *fixed_var, const double *bin_scale, int64_t B,
-                            const double *theta, size_t device_bytes, double *logL, int32_t *info);
+                            const double *theta, size_t device_bytes, int32_t lanes, double *logL,
+                            int32_t *info);
+
+/*
+ * The schedule eor_loglike_host follows for these arguments, without running
+ * it (host only, no device call): lanes_out, the tile columns per pass
+ * (cols_per_pass), the tiles of a lane's window of earlier columns
+ * (window_tiles) and the host <-> device bytes per theta (link_bytes: A and
+ * L once each, and the rows of every earlier tile column below a pass once
+ * per pass). Any output pointer may be NULL. Errors as eor_loglike_host's
+ * for the same arguments (EOR_ERR_ARG, EOR_ERR_OOM).
+ */
+eor_status eor_loglike_host_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes,
+                                 int32_t *lanes_out, int64_t *cols_per_pass, int64_t *window_tiles,
+                                 int64_t *link_bytes);
 
 /*
  * Instrument forward model (the step before the likelihood, from the

@@ -97,7 +97,8 @@ def lib() -> ctypes.CDLL:
         L.eor_probe_fp64_mfma.argtypes = [ctypes.c_int, _I64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
         L.eor_loglike_host.argtypes = [ctypes.c_int, _I64, _P, _I64, _P, ctypes.c_double, ctypes.c_double, _I32,
-                                       _P, _P, _P, _I64, _P, ctypes.c_size_t, _P, _P]
+                                       _P, _P, _P, _I64, _P, ctypes.c_size_t, _I32, _P, _P]
+        L.eor_loglike_host_plan.argtypes = [_I64, _I32, ctypes.c_size_t, _I32, _P, _P, _P, _P]
         L.eor_forward_model.argtypes = [_I64, _I64, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, ctypes.c_double,
                                         _P, _I64, _P]
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
@@ -107,7 +108,8 @@ def lib() -> ctypes.CDLL:
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
                      "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
-                     "eor_compact_rows", "eor_probe_fp64_mfma", "eor_forward_model", "eor_loglike_host"):
+                     "eor_compact_rows", "eor_probe_fp64_mfma", "eor_forward_model", "eor_loglike_host",
+                     "eor_loglike_host_plan"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -404,10 +406,11 @@ def compact_rows(keep, rows=None):
     return (None if out is None else out[:c]), idx[:c], c
 
 
-def loglike_host(A, dbar, c, K0, n_k, bin_of, fixed_var, bin_scale, theta, device_bytes, device=0):
+def loglike_host(A, dbar, c, K0, n_k, bin_of, fixed_var, bin_scale, theta, device_bytes, device=0, lanes=0):
     """(logL [B], info [B]) of eor_loglike_host: A (complex128 [n, n], host,
     lower triangle read) and the rest in host memory; the device uses at most
-    `device_bytes` (Sigma factored out of core, one theta at a time)."""
+    `device_bytes` (Sigma factored out of core, `lanes` theta at a time, 0 =
+    the library's choice)."""
     A = np.asarray(A, dtype=np.complex128)
     if not A.flags.c_contiguous:
         A = np.ascontiguousarray(A)
@@ -422,8 +425,18 @@ def loglike_host(A, dbar, c, K0, n_k, bin_of, fixed_var, bin_scale, theta, devic
     check(lib().eor_loglike_host(int(device), n, A.ctypes.data, A.shape[1], dbar.ctypes.data, float(c), float(K0),
                                  int(n_k), bin_of.ctypes.data, fixed_var.ctypes.data,
                                  None if bs is None else bs.ctypes.data, B, theta.ctypes.data, int(device_bytes),
-                                 logL.ctypes.data, info.ctypes.data))
+                                 int(lanes), logL.ctypes.data, info.ctypes.data))
     return logL, info
+
+
+def loglike_host_plan(n, n_k, device_bytes, lanes=0):
+    """The schedule eor_loglike_host follows (host only): dict of lanes,
+    cols_per_pass, window_tiles and link_bytes (host <-> device per theta)."""
+    lo = ctypes.c_int32()
+    J, W, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib().eor_loglike_host_plan(int(n), int(n_k), int(device_bytes), int(lanes), ctypes.byref(lo),
+                                      ctypes.byref(J), ctypes.byref(W), ctypes.byref(nb)))
+    return {"lanes": lo.value, "cols_per_pass": J.value, "window_tiles": W.value, "link_bytes": nb.value}
 
 
 def forward_model(freq, bl, lm, beam, uv, Z, norm, out=None):

@@ -1,8 +1,11 @@
 // Likelihood with Sigma factored through a bounded device window: the
 // out-of-core case (the paper's MAGMA footnote: matrices larger than the
-// GPU's memory). A stays in the caller's host memory, the factor L of the
-// current theta in a pinned host buffer of the library, and the device holds
-// a pass of tile columns of 64 x 64 tiles plus a window of earlier columns of L.
+// GPU's memory). A stays in host memory (a pinned packed copy), the factor L
+// of a theta in a pinned host buffer of the library, and the device holds a
+// pass of tile columns of 64 x 64 tiles plus a window of earlier columns of
+// L. Up to four theta run at once, each on a lane of its own (a stream, an
+// equal share of the device budget, a host factor), so that one lane's
+// copies and launch gaps overlap another's kernels.
 //
 // Blocked Cholesky over passes of J tile columns [j0, j1) (as many as half
 // the device window holds), left-looking across passes:
@@ -21,8 +24,12 @@
 // tile column below any row is one contiguous block and every transfer of
 // the schedule is a single DMA. The tile products run on FP64 MFMA with
 // three real products per complex step.
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <memory>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -181,32 +188,55 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
                                                         int64_t j, OocState *st) {
     __shared__ double2 S[OT][OT + 1];
     __shared__ double2 V[OT][OT + 1];
-    __shared__ double sq[OT], isq[OT];
+    __shared__ double sq[OT], isq[OT], lsq[OT];
     __shared__ double2 yj[OT];
     __shared__ int fail_col;
     if (st->info != 0) return;
     const int tid = threadIdx.x;
-    for (int e = tid; e < OT2; e += 256) {
-        S[e / OT][e % OT] = C0[e];
-        V[e / OT][e % OT] = make_double2(0.0, 0.0);
+    {
+        // all sixteen loads of the thread in flight before the first LDS store
+        double2 v[OT2 / 256];
+#pragma unroll
+        for (int u = 0; u < OT2 / 256; ++u) v[u] = C0[tid + 256 * u];
+#pragma unroll
+        for (int u = 0; u < OT2 / 256; ++u) {
+            const int e = tid + 256 * u;
+            S[e / OT][e % OT] = v[u];
+            V[e / OT][e % OT] = make_double2(0.0, 0.0);
+        }
     }
     if (tid == 0) fail_col = 0;
     __syncthreads();
+    if (tid < OT) yj[tid] = w[OT * j + tid];  // w_j, read by the solve below
+    // thread (row r = tid / 4, part = tid % 4) updates S[r][s] for s = c+1+part,
+    // c+5+part, ... <= r: the later rows' lower triangle, no index division
+    const int er = tid >> 2, ep = tid & 3;
     for (int c = 0; c < OT; ++c) {
         const double dcc = S[c][c].x;
         if (!(dcc > 0.0) || !isfinite(dcc)) {
             if (tid == 0) fail_col = c + 1;
             break;  // uniform: every thread reads the same value
         }
-        const double inv = 1.0 / dcc;
-        const int m = OT - 1 - c;
-        for (int e = tid; e < m * m; e += 256) {
-            const int r = c + 1 + e / m, s = c + 1 + e % m;
-            if (s <= r) {
-                const double2 a = S[r][c], b = S[s][c];
-                S[r][s] = make_double2(S[r][s].x - (a.x * b.x + a.y * b.y) * inv,
-                                       S[r][s].y - (a.y * b.x - a.x * b.y) * inv);
+        if (er > c) {
+            const double inv = 1.0 / dcc;
+            const double2 a = S[er][c];
+            const double ar = a.x * inv, ai = a.y * inv;
+            auto upd = [&](double2 x, double2 b) {
+                return make_double2(x.x - (ar * b.x + ai * b.y), x.y - (ai * b.x - ar * b.y));
+            };
+            int s = c + 1 + ep;
+            // four updates at a time, their eight LDS reads issued before any write
+            for (; s + 12 <= er; s += 16) {
+                double2 b[4], x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    b[u] = S[s + 4 * u][c];
+                    x[u] = S[er][s + 4 * u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) S[er][s + 4 * u] = upd(x[u], b[u]);
             }
+            for (; s <= er; s += 4) S[er][s] = upd(S[er][s], S[s][c]);
         }
         __syncthreads();
     }
@@ -218,6 +248,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     if (tid < OT) {
         sq[tid] = sqrt(S[tid][tid].x);
         isq[tid] = 1.0 / sq[tid];
+        lsq[tid] = log(sq[tid]);
     }
     __syncthreads();
     // inverse of the lower factor: four lanes per column (one wave holds
@@ -230,12 +261,25 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
         for (int r = 1; r < OT; ++r) {
             if (r > cc) {
                 double sr = 0.0, si = 0.0;
-                for (int t = cc + part; t < r; t += 4) {
-                    const double2 a = S[r][t], b = V[t][cc];
-                    const double lt = isq[t];
+                auto acc = [&](double2 a, double2 b, double lt) {
                     sr += (a.x * b.x - a.y * b.y) * lt;
                     si += (a.x * b.y + a.y * b.x) * lt;
+                };
+                int t = cc + part;
+                // the reads of four terms issued together, the terms added in order
+                for (; t + 12 < r; t += 16) {
+                    double2 a[4], b[4];
+                    double lt[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = S[r][t + 4 * u];
+                        b[u] = V[t + 4 * u][cc];
+                        lt[u] = isq[t + 4 * u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc(a[u], b[u], lt[u]);
                 }
+                for (; t < r; t += 4) acc(S[r][t], V[t][cc], isq[t]);
                 sr += __shfl_xor(sr, 1);
                 si += __shfl_xor(si, 1);
                 sr += __shfl_xor(sr, 2);
@@ -256,14 +300,18 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
         C0[e] = l;
         Linv[e] = c <= r ? V[r][c] : make_double2(0.0, 0.0);
     }
-    // y_j = Linv w_j
+    // y_j = Linv w_j (w_j in yj since the start; every thread reads it before
+    // the rows' results replace it)
+    double sr = 0.0, si = 0.0;
     if (tid < OT) {
-        double sr = 0.0, si = 0.0;
         for (int t = 0; t <= tid; ++t) {
-            const double2 a = V[tid][t], b = w[OT * j + t];
+            const double2 a = V[tid][t], b = yj[t];
             sr += a.x * b.x - a.y * b.y;
             si += a.x * b.y + a.y * b.x;
         }
+    }
+    __syncthreads();
+    if (tid < OT) {
         yj[tid] = make_double2(sr, si);
         y[OT * j + tid] = yj[tid];
     }
@@ -271,7 +319,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     if (tid == 0) {
         double ld = 0.0, qd = 0.0;
         for (int d = 0; d < OT; ++d) {
-            ld += log(sq[d]);
+            ld += lsq[d];
             qd += yj[d].x * yj[d].x + yj[d].y * yj[d].y;
         }
         st->logdet += 2.0 * ld;
@@ -344,15 +392,121 @@ struct DevBuf {
     }
 };
 
+// The schedule of a call, fixed by its arguments (never by the number of
+// theta, so that a theta's result does not depend on the batch it is in).
+struct OocPlan {
+    int lanes = 1;      // theta factored at once, each on its own stream
+    int64_t N = 0;      // tile rows
+    int64_t n_pad = 0;  // N * 64
+    int64_t J = 0;      // tile columns per pass
+    int64_t capC = 0;   // tiles of a lane's pass buffer (J N)
+    int64_t cap = 0;    // tiles of a lane's window of earlier columns (>= N)
+    size_t shared_b = 0, lane_fixed_b = 0;
+    int64_t link_bytes = 0;  // host <-> device bytes per theta
+};
+
+constexpr size_t TILE_B = (size_t)OT2 * sizeof(double2);
+constexpr int MAX_LANES = 4;
+
+int64_t ntiles(int64_t N) { return N * (N + 1) / 2; }
+
+// Device bytes: shared dbar, bin map, fixed variances and scales; per lane
+// Linv, w and y, the state and theta and result slots, then the lane's
+// share of what is left in tiles, half of it for the pass (whole tile
+// columns) and the rest for the window of earlier columns.
+eor_status ooc_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes, OocPlan &p) {
+    p.N = (n + OT - 1) / OT;
+    p.n_pad = p.N * OT;
+    p.shared_b = (size_t)p.n_pad * sizeof(double2) + (size_t)n * (sizeof(int32_t) + sizeof(double)) +
+                 (size_t)n_k * sizeof(double) + 4096;
+    p.lane_fixed_b = TILE_B + 2 * (size_t)p.n_pad * sizeof(double2) + (size_t)n_k * sizeof(double) + 1024;
+    auto avail_of = [&](int L) -> int64_t {
+        if (device_bytes <= p.shared_b) return -1;
+        const size_t per = (device_bytes - p.shared_b) / (size_t)L;
+        return per < p.lane_fixed_b ? -1 : (int64_t)((per - p.lane_fixed_b) / TILE_B);
+    };
+    int L = lanes;
+    if (lanes == 0) {
+        // as many lanes (up to four) as keep at least min(N, 8) tile columns
+        // per pass each, and their pinned factors (plus the packed A) within
+        // half of the host's physical memory
+        L = 1;
+        const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
+        const double host = pages > 0 && page > 0 ? (double)pages * (double)page : 0.0;
+        for (int cand = MAX_LANES; cand > 1; cand /= 2) {
+            const int64_t av = avail_of(cand);
+            const bool fits_host = (double)(cand + 1) * (double)ntiles(p.N) * (double)TILE_B <= 0.5 * host;
+            if (av >= 2 * std::min<int64_t>(p.N, 8) * p.N && fits_host) {
+                L = cand;
+                break;
+            }
+        }
+    } else if (lanes < 1 || lanes > MAX_LANES) {
+        return fail_status(EOR_ERR_ARG, "eor_loglike_host: lanes outside 0..4");
+    }
+    const int64_t avail = avail_of(L);
+    if (avail < 2 * p.N) return fail_status(EOR_ERR_OOM, "eor_loglike_host: device_bytes below two columns of tiles per lane");
+    p.lanes = L;
+    p.J = std::max<int64_t>(1, std::min<int64_t>(p.N, (avail / 2) / p.N));
+    p.capC = p.J * p.N;
+    p.cap = avail - p.capC;  // >= N
+    int64_t t = 2 * ntiles(p.N);
+    for (int64_t j0 = 0; j0 < p.N; j0 += p.J) t += j0 * (p.N - j0);
+    p.link_bytes = t * (int64_t)TILE_B;
+    return EOR_OK;
+}
+
+// One lane: a stream, its device buffers and its pinned host factor. The
+// destructor waits for the lane's work before anything is freed.
+struct OocLane {
+    hipStream_t s = nullptr;
+    DevBuf<double2> C, Lw, Linv, w, y;
+    DevBuf<double> theta, out;
+    DevBuf<int32_t> info;
+    DevBuf<OocState> st;
+    double2 *Lh = nullptr;  // pinned host factor, tile columns packed
+    ~OocLane() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        if (Lh) (void)hipHostFree(Lh);
+    }
+};
+
+template <typename T>
+struct PinnedBuf {
+    T *p = nullptr;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
 }  // namespace
 
 }  // namespace eor
 
+extern "C" eor_status eor_loglike_host_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes,
+                                            int32_t *lanes_out, int64_t *cols_per_pass, int64_t *window_tiles,
+                                            int64_t *link_bytes) {
+    using namespace eor;
+    if (n < 1 || n_k < 1 || n > ((int64_t)1 << 22))
+        return fail_status(EOR_ERR_ARG, "eor_loglike_host_plan: bad sizes");
+    OocPlan p;
+    const eor_status r = ooc_plan(n, n_k, device_bytes, lanes, p);
+    if (r != EOR_OK) return r;
+    if (lanes_out) *lanes_out = p.lanes;
+    if (cols_per_pass) *cols_per_pass = p.J;
+    if (window_tiles) *window_tiles = p.cap;
+    if (link_bytes) *link_bytes = p.link_bytes;
+    return EOR_OK;
+}
+
 extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, int64_t ldA,
                                        const double *dbar, double c, double K0, int32_t n_k,
                                        const int32_t *bin_of, const double *fixed_var, const double *bin_scale,
-                                       int64_t B, const double *theta, size_t device_bytes, double *logL,
-                                       int32_t *info) {
+                                       int64_t B, const double *theta, size_t device_bytes, int32_t lanes,
+                                       double *logL, int32_t *info) {
     using namespace eor;
     if (n < 1 || n_k < 1 || B < 0 || ldA < n || !A || !dbar || !bin_of || !fixed_var || !theta || !logL)
         return fail_status(EOR_ERR_ARG, "eor_loglike_host: bad sizes or NULL array");
@@ -362,135 +516,163 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
         if (bin_of[d] < 0 && !(fixed_var[d] > 0.0 && std::isfinite(fixed_var[d])))
             return fail_status(EOR_ERR_ARG, "eor_loglike_host: fixed variance must be positive and finite");
     }
+    OocPlan P;
+    eor_status r = ooc_plan(n, n_k, device_bytes, lanes, P);
+    if (r != EOR_OK) return r;
     if (B == 0) return EOR_OK;
-    const int64_t N = (n + OT - 1) / OT, n_pad = N * OT;
-    const size_t tile_b = (size_t)OT2 * sizeof(double2);
-    // device: Linv (1 tile), vectors and tables, then tiles shared between the
-    // super-column (capC) and the window of earlier columns (capW)
-    const size_t fixed_b = tile_b + 2 * (size_t)n_pad * sizeof(double2) + (size_t)n * (sizeof(int32_t) + sizeof(double)) +
-                           4096;
-    if (device_bytes < fixed_b + 2 * (size_t)N * tile_b)
-        return fail_status(EOR_ERR_OOM, "eor_loglike_host: device_bytes below two columns of tiles");
-    const int64_t avail = (int64_t)((device_bytes - fixed_b) / tile_b);
-    const int64_t J = std::max<int64_t>(1, std::min<int64_t>(N, (avail / 2) / N));  // tile columns per pass
-    const int64_t capC = J * N, cap = avail - capC;                                  // cap >= N
+    const int64_t N = P.N, n_pad = P.n_pad, J = P.J, capC = P.capC, cap = P.cap;
+    const int S = (int)std::min<int64_t>(P.lanes, B);  // lanes in use
     int prev = -1;
     (void)hipGetDevice(&prev);
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) return hip_status(e, "eor_loglike_host: device");
-    hipStream_t s = nullptr;
-    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_status(e, "eor_loglike_host: stream");
-    DevBuf<double2> C, Lw, Linv, w, y, dbar_d;
+    struct Restore {
+        int d;
+        ~Restore() {
+            if (d >= 0) (void)hipSetDevice(d);
+        }
+    } restore{prev};
+    // declared before the lanes, so destroyed after them (the lanes wait for their streams)
+    DevBuf<double2> dbar_d;
     DevBuf<int32_t> bin_d;
-    DevBuf<double> fix_d, scale_d, theta_d, out_d;
-    DevBuf<int32_t> info_d;
-    DevBuf<OocState> st;
-    double2 *Lh = nullptr;  // pinned host factor, tile columns packed
-    double2 *Ah = nullptr;  // pinned host copy of A, same packing
-    auto done = [&](eor_status r) {
-        if (s) (void)hipStreamDestroy(s);
-        if (Lh) (void)hipHostFree(Lh);
-        if (Ah) (void)hipHostFree(Ah);
-        if (prev >= 0) (void)hipSetDevice(prev);
-        return r;
-    };
-    const int64_t ntile = N * (N + 1) / 2;
+    DevBuf<double> fix_d, scale_d;
+    PinnedBuf<double2> Ah;  // pinned host copy of A, tile columns packed
+    PinnedBuf<double> theta_h, out_h;
+    PinnedBuf<int32_t> info_h;
+    std::unique_ptr<OocLane[]> lane(new OocLane[S]);
+    const int64_t ntile = ntiles(N);
     auto col_off = [&](int64_t k) { return k * N - k * (k - 1) / 2; };  // first tile of tile column k
-    e = hipMalloc(&C.p, (size_t)capC * tile_b);
-    if (e == hipSuccess) e = hipMalloc(&Lw.p, (size_t)cap * tile_b);
-    if (e == hipSuccess) e = hipMalloc(&Linv.p, tile_b);
-    if (e == hipSuccess) e = hipMalloc(&w.p, n_pad * sizeof(double2));
-    if (e == hipSuccess) e = hipMalloc(&y.p, n_pad * sizeof(double2));
-    if (e == hipSuccess) e = hipMalloc(&dbar_d.p, n_pad * sizeof(double2));
+    e = hipMalloc(&dbar_d.p, n_pad * sizeof(double2));
     if (e == hipSuccess) e = hipMalloc(&bin_d.p, n * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&fix_d.p, n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&scale_d.p, n_k * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&theta_d.p, (size_t)B * n_k * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&out_d.p, (size_t)B * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&info_d.p, (size_t)B * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&st.p, sizeof(OocState));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&Lh, (size_t)ntile * tile_b, 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&Ah, (size_t)ntile * tile_b, 0);
-    if (e != hipSuccess) return done(hip_status(e, "eor_loglike_host: allocation"));
-    // A's lower tiles, zero-padded past n, into the packed host copy
+    if (e == hipSuccess) e = hipHostMalloc((void **)&Ah.p, (size_t)ntile * TILE_B, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&theta_h.p, (size_t)B * n_k * sizeof(double), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&out_h.p, (size_t)B * sizeof(double), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&info_h.p, (size_t)B * sizeof(int32_t), 0);
+    for (int l = 0; l < S && e == hipSuccess; ++l) {
+        OocLane &L = lane[l];
+        e = hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipMalloc(&L.C.p, (size_t)capC * TILE_B);
+        if (e == hipSuccess) e = hipMalloc(&L.Lw.p, (size_t)cap * TILE_B);
+        if (e == hipSuccess) e = hipMalloc(&L.Linv.p, TILE_B);
+        if (e == hipSuccess) e = hipMalloc(&L.w.p, n_pad * sizeof(double2));
+        if (e == hipSuccess) e = hipMalloc(&L.y.p, n_pad * sizeof(double2));
+        if (e == hipSuccess) e = hipMalloc(&L.theta.p, n_k * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&L.out.p, sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&L.info.p, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&L.st.p, sizeof(OocState));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&L.Lh, (size_t)ntile * TILE_B, 0);
+    }
+    if (e != hipSuccess) return hip_status(e, "eor_loglike_host: allocation");
+    // A's lower tiles, zero-padded past n, into the packed host copy: tile
+    // columns k = t, t + T, ... on host thread t of T (disjoint tiles)
     const double2 *Asrc = reinterpret_cast<const double2 *>(A);
-    for (int64_t k = 0; k < N; ++k)
-        for (int64_t i = k; i < N; ++i) {
-            double2 *tile = Ah + (col_off(k) + (i - k)) * OT2;
-            for (int r = 0; r < OT; ++r) {
-                const int64_t gr = OT * i + r;
-                double2 *dst = tile + r * OT;
-                const int64_t cols = std::min<int64_t>(OT, n - OT * k);
-                if (gr < n) {
-                    std::copy(Asrc + gr * ldA + OT * k, Asrc + gr * ldA + OT * k + cols, dst);
-                    std::fill(dst + cols, dst + OT, make_double2(0.0, 0.0));
-                } else {
-                    std::fill(dst, dst + OT, make_double2(0.0, 0.0));
+    auto pack = [&](int64_t first, int64_t step) {
+        for (int64_t k = first; k < N; k += step)
+            for (int64_t i = k; i < N; ++i) {
+                double2 *tile = Ah.p + (col_off(k) + (i - k)) * OT2;
+                for (int rr = 0; rr < OT; ++rr) {
+                    const int64_t gr = OT * i + rr;
+                    double2 *dst = tile + rr * OT;
+                    const int64_t cols = std::min<int64_t>(OT, n - OT * k);
+                    if (gr < n) {
+                        std::copy(Asrc + gr * ldA + OT * k, Asrc + gr * ldA + OT * k + cols, dst);
+                        std::fill(dst + cols, dst + OT, make_double2(0.0, 0.0));
+                    } else {
+                        std::fill(dst, dst + OT, make_double2(0.0, 0.0));
+                    }
                 }
             }
+    };
+    {
+        const int64_t hc = (int64_t)std::thread::hardware_concurrency();
+        const int T = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(8, N), hc));
+        std::vector<std::thread> pool;
+        int started = 0;
+        try {
+            for (int t = 1; t < T; ++t) {
+                pool.emplace_back(pack, (int64_t)t, (int64_t)T);
+                ++started;
+            }
+        } catch (...) {
+            // a thread that could not start: its share is packed below
         }
+        pack(0, T);
+        for (int t = started + 1; t < T; ++t) pack(t, T);
+        for (auto &th : pool) th.join();
+    }
+    std::copy(theta, theta + B * n_k, theta_h.p);
     std::vector<double> scale_h(n_k, 1.0);
     if (bin_scale) std::copy(bin_scale, bin_scale + n_k, scale_h.begin());
-    e = hipMemsetAsync(dbar_d.p, 0, n_pad * sizeof(double2), s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dbar_d.p, dbar, n * sizeof(double2), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(bin_d.p, bin_of, n * sizeof(int32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(fix_d.p, fixed_var, n * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(scale_d.p, scale_h.data(), n_k * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(theta_d.p, theta, (size_t)B * n_k * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return done(hip_status(e, "eor_loglike_host: inputs"));
+    hipStream_t s0 = lane[0].s;
+    e = hipMemsetAsync(dbar_d.p, 0, n_pad * sizeof(double2), s0);
+    if (e == hipSuccess) e = hipMemcpyAsync(dbar_d.p, dbar, n * sizeof(double2), hipMemcpyHostToDevice, s0);
+    if (e == hipSuccess) e = hipMemcpyAsync(bin_d.p, bin_of, n * sizeof(int32_t), hipMemcpyHostToDevice, s0);
+    if (e == hipSuccess) e = hipMemcpyAsync(fix_d.p, fixed_var, n * sizeof(double), hipMemcpyHostToDevice, s0);
+    if (e == hipSuccess) e = hipMemcpyAsync(scale_d.p, scale_h.data(), n_k * sizeof(double), hipMemcpyHostToDevice, s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(s0);
+    if (e != hipSuccess) return hip_status(e, "eor_loglike_host: inputs");
 
-    for (int64_t b = 0; b < B; ++b) {
-        hipLaunchKernelGGL(ooc_reset_kernel, dim3(1), dim3(1), 0, s, st.p);
-        e = hipMemcpyAsync(w.p, dbar_d.p, n_pad * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    // theta b on lane b mod S; each lane's theta run in order on its stream,
+    // the lanes concurrently
+    for (int64_t b = 0; b < B && e == hipSuccess; ++b) {
+        OocLane &L = lane[b % S];
+        hipStream_t s = L.s;
+        e = hipMemcpyAsync(L.theta.p, theta_h.p + b * n_k, n_k * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(ooc_reset_kernel, dim3(1), dim3(1), 0, s, L.st.p);
+        e = hipMemcpyAsync(L.w.p, dbar_d.p, n_pad * sizeof(double2), hipMemcpyDeviceToDevice, s);
         for (int64_t j0 = 0; e == hipSuccess && j0 < N; j0 += J) {
             const int64_t j1 = std::min<int64_t>(N, j0 + J), nt = col_off(j1) - col_off(j0), rows0 = N - j0;
             // tile columns j0 .. j1-1 of A: one contiguous block
-            e = hipMemcpyAsync(C.p, Ah + col_off(j0) * OT2, (size_t)nt * tile_b, hipMemcpyHostToDevice, s);
+            e = hipMemcpyAsync(L.C.p, Ah.p + col_off(j0) * OT2, (size_t)nt * TILE_B, hipMemcpyHostToDevice, s);
             if (e != hipSuccess) break;
             for (int64_t j = j0; j < j1; ++j)
-                hipLaunchKernelGGL(ooc_diag_kernel, dim3(1), dim3(OT), 0, s, C.p + (col_off(j) - col_off(j0)) * OT2,
-                                   j, n, theta_d.p + b * n_k, bin_d.p, fix_d.p, scale_d.p, st.p);
+                hipLaunchKernelGGL(ooc_diag_kernel, dim3(1), dim3(OT), 0, s, L.C.p + (col_off(j) - col_off(j0)) * OT2,
+                                   j, n, L.theta.p, bin_d.p, fix_d.p, scale_d.p, L.st.p);
             // earlier tile columns, rows j0 .. N-1, in windows of W columns, each read once per pass
             const int64_t W = std::max<int64_t>(1, std::min<int64_t>(j0, cap / rows0));
             for (int64_t k0 = 0; k0 < j0; k0 += W) {
                 const int64_t wk = std::min<int64_t>(W, j0 - k0);
                 for (int64_t k = 0; k < wk && e == hipSuccess; ++k) {
                     const int64_t kk = k0 + k;
-                    e = hipMemcpyAsync(Lw.p + k * rows0 * OT2, Lh + (col_off(kk) + (j0 - kk)) * OT2,
-                                       (size_t)rows0 * tile_b, hipMemcpyHostToDevice, s);
+                    e = hipMemcpyAsync(L.Lw.p + k * rows0 * OT2, L.Lh + (col_off(kk) + (j0 - kk)) * OT2,
+                                       (size_t)rows0 * TILE_B, hipMemcpyHostToDevice, s);
                 }
                 if (e != hipSuccess) break;
-                hipLaunchKernelGGL(ooc_window_kernel, dim3((unsigned)nt), dim3(256), 0, s, C.p, Lw.p, (int)wk, j0, j1, N,
-                                   st.p);
+                hipLaunchKernelGGL(ooc_window_kernel, dim3((unsigned)nt), dim3(256), 0, s, L.C.p, L.Lw.p, (int)wk, j0,
+                                   j1, N, L.st.p);
             }
             if (e != hipSuccess) break;
             // the pass's own columns, left to right; each finished column updates
             // the later columns of the pass at once
             for (int64_t j = j0; j < j1; ++j) {
                 const int64_t rows = N - j;
-                double2 *Cj = C.p + (col_off(j) - col_off(j0)) * OT2;
-                hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, Cj, Linv.p, w.p, y.p, j, st.p);
+                double2 *Cj = L.C.p + (col_off(j) - col_off(j0)) * OT2;
+                hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, Cj, L.Linv.p, L.w.p, L.y.p, j, L.st.p);
                 if (rows > 1)
-                    hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, Cj, Linv.p, w.p,
-                                       y.p, j, st.p);
+                    hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, Cj, L.Linv.p,
+                                       L.w.p, L.y.p, j, L.st.p);
                 if (j + 1 < j1)
                     hipLaunchKernelGGL(ooc_pass_kernel, dim3((unsigned)(col_off(j1) - col_off(j + 1))), dim3(256), 0,
-                                       s, C.p, j, j0, j1, N, st.p);
+                                       s, L.C.p, j, j0, j1, N, L.st.p);
             }
             // tile columns j0 .. j1-1 of L to the host factor: one contiguous block
-            e = hipMemcpyAsync(Lh + col_off(j0) * OT2, C.p, (size_t)nt * tile_b, hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(L.Lh + col_off(j0) * OT2, L.C.p, (size_t)nt * TILE_B, hipMemcpyDeviceToHost, s);
         }
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(ooc_finish_kernel, dim3(1), dim3(1), 0, s, st.p, K0, c, out_d.p + b, info_d.p + b);
+        hipLaunchKernelGGL(ooc_finish_kernel, dim3(1), dim3(1), 0, s, L.st.p, K0, c, L.out.p, L.info.p);
+        e = hipMemcpyAsync(out_h.p + b, L.out.p, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(info_h.p + b, L.info.p, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(logL, out_d.p, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && info)
-        e = hipMemcpyAsync(info, info_d.p, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return done(hip_status(e, "eor_loglike_host"));
-    return done(EOR_OK);
+    for (int l = 0; l < S; ++l) {
+        const hipError_t e2 = hipStreamSynchronize(lane[l].s);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_status(e, "eor_loglike_host");
+    std::copy(out_h.p, out_h.p + B, logL);
+    if (info) std::copy(info_h.p, info_h.p + B, info);
+    return EOR_OK;
 }

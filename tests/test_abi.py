@@ -60,12 +60,48 @@ def test_argument_errors_without_gpu():
     th = np.zeros((1, 2))
     out = np.zeros(1)
     inf_ = np.zeros(1, dtype=np.int32)
-    args = lambda n, b, f, nb: (0, n, A.ctypes.data, 4, db.ctypes.data, 0.0, 0.0, 2, b.ctypes.data, f.ctypes.data,
-                                None, 1, th.ctypes.data, nb, out.ctypes.data, inf_.ctypes.data)
+    args = lambda n, b, f, nb, lanes=0: (0, n, A.ctypes.data, 4, db.ctypes.data, 0.0, 0.0, 2, b.ctypes.data,
+                                         f.ctypes.data, None, 1, th.ctypes.data, nb, lanes, out.ctypes.data,
+                                         inf_.ctypes.data)
     assert L.eor_loglike_host(*args(0, bins, fv, 1 << 30)) == eor.EOR_ERR_ARG
     assert L.eor_loglike_host(*args(4, np.array([0, 2, 1, -1], dtype=np.int32), fv, 1 << 30)) == eor.EOR_ERR_ARG
     assert L.eor_loglike_host(*args(4, bins, np.zeros(4), 1 << 30)) == eor.EOR_ERR_ARG
     assert L.eor_loglike_host(*args(4, bins, fv, 1024)) == eor.EOR_ERR_OOM
+    assert L.eor_loglike_host(*args(4, bins, fv, 1 << 30, 5)) == eor.EOR_ERR_ARG
+    assert L.eor_loglike_host(*args(4, bins, fv, 1 << 30, -1)) == eor.EOR_ERR_ARG
+
+
+def test_out_of_core_plan():
+    """The out-of-core schedule, computed on the host without a device call:
+    pass width from the device budget per lane (half of a lane's tiles, in
+    whole tile columns), the automatic lane count, and the host <-> device
+    bytes per theta (A and L once each, plus every earlier tile column's rows
+    below a pass, once per pass)."""
+    import paper_2501_12928_amd as eor
+    tile = 64 * 64 * 16
+    N = 64
+    # one lane at 256 MiB, n = 4096: 4091 tiles after the vectors -> 31 columns per pass
+    p = eor.loglike_host_plan(4096, 12, 256 << 20, lanes=1)
+    assert p["lanes"] == 1 and p["cols_per_pass"] == 31
+    assert p["window_tiles"] >= N
+    moved = 2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 31))
+    assert p["link_bytes"] == moved * tile
+    # automatic: four lanes would leave 1020 tiles each (< 2 x 8 x 64), two leave 2044 -> 15 columns
+    p = eor.loglike_host_plan(4096, 12, 256 << 20)
+    assert p["lanes"] == 2 and p["cols_per_pass"] == 15
+    assert p["link_bytes"] == (2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 15))) * tile
+    # the smallest budget of the GPU tests (n = 333: 6 tile rows, 14 tiles): one lane, one column per pass
+    p = eor.loglike_host_plan(333, 4, 14 * tile)
+    assert p == {"lanes": 1, "cols_per_pass": 1, "window_tiles": 6,
+                 "link_bytes": (2 * 21 + sum(j0 * (6 - j0) for j0 in range(6))) * tile}
+    # a roomy budget: four lanes, each holding the whole matrix in one pass
+    p = eor.loglike_host_plan(333, 4, 1 << 30)
+    assert p["lanes"] == 4 and p["cols_per_pass"] == 6 and p["link_bytes"] == 2 * 21 * tile
+    # explicit lanes that do not fit, and arguments out of range
+    L = eor.lib()
+    assert L.eor_loglike_host_plan(333, 4, 14 * tile, 2, None, None, None, None) == eor.EOR_ERR_OOM
+    assert L.eor_loglike_host_plan(333, 4, 1 << 30, 5, None, None, None, None) == eor.EOR_ERR_ARG
+    assert L.eor_loglike_host_plan(0, 4, 1 << 30, 0, None, None, None, None) == eor.EOR_ERR_ARG
 
 
 def test_product_package_does_not_reference_oracle():

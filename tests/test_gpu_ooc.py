@@ -1,9 +1,12 @@
-"""Out-of-core likelihood (eor_loglike_host): A in host memory, the factor in
-a pinned host buffer, the device holding a column of tiles and a window of
-earlier columns. Checked against the FP64 oracle: on the oracle's own A at
-a ragged size with the smallest device window and with a roomy one, at the
-full 20000 x 4096 size against the stored oracle values, and on the failure
-paths (invalid theta, a pivot that is not positive)."""
+"""Out-of-core likelihood (eor_loglike_host): A in host memory, each theta's
+factor in a pinned host buffer, the device holding a pass of tile columns and
+a window of earlier columns, up to four theta at once on their own streams.
+Checked against the FP64 oracle: on the oracle's own A at a ragged size with
+the smallest device window and with a roomy one, with several lanes and
+several passes, at the full 20000 x 4096 size against the stored oracle
+values, and on the failure paths (invalid theta, a pivot that is not
+positive); and bit for bit across lane counts and batch orders where the
+schedule is the same."""
 import json
 import os
 
@@ -34,6 +37,48 @@ def test_ooc_matches_oracle_on_its_own_A(orc, budget):
     print(f"gpu: out-of-core logL n=333 budget={nbytes}", flush=True)
     got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
                                  inst.theta, nbytes)
+    assert np.all(info == 0)
+    assert np.all(np.abs(got - ref) <= tol(ref))
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
+
+
+def test_ooc_lanes_give_the_same_bits(orc):
+    """With a budget that holds the whole matrix in one pass whatever the lane
+    count, every theta runs the same kernels in the same order on its lane:
+    lanes 1, 2 and 4 and a reversed batch give identical logL (7 theta, not a
+    multiple of the lanes)."""
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=73, m=700, n=260, n_k=4, n_theta=7)
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    budget = 1 << 30
+    for lanes in (1, 2, 4):
+        assert eor.loglike_host_plan(inst.n, inst.n_k, budget, lanes)["cols_per_pass"] == 5
+    print("gpu: out-of-core lanes 1, 2, 4, n=260", flush=True)
+    runs = [eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, inst.theta,
+                             budget, lanes=lanes) for lanes in (1, 2, 4)]
+    for got, info in runs:
+        assert np.all(info == 0)
+        assert np.array_equal(got, runs[0][0])
+    rev, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
+                                 inst.theta[::-1], budget, lanes=2)
+    assert np.all(info == 0) and np.array_equal(rev[::-1], runs[0][0])
+
+
+def test_ooc_two_lanes_several_passes(orc):
+    """Two lanes, each with a window that takes three columns per pass (n =
+    700: 11 tile rows, 4 passes), 9 theta against the oracle."""
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=74, m=1500, n=700, n_k=5, n_theta=9)
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    ref, rinfo = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, inst.theta)
+    assert np.all(rinfo == 0)
+    N = 11
+    budget = 2 * ((2 * 3 * N + 2) * TILE_BYTES + 4 * N * 64 * 16 + 8192)
+    plan = eor.loglike_host_plan(inst.n, inst.n_k, budget, 2)
+    assert plan["lanes"] == 2 and plan["cols_per_pass"] == 3
+    print(f"gpu: out-of-core two lanes n=700 budget={budget}", flush=True)
+    got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
+                                 inst.theta, budget, lanes=2)
     assert np.all(info == 0)
     assert np.all(np.abs(got - ref) <= tol(ref))
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
