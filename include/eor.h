@@ -394,7 +394,7 @@ eor_status eor_loglike_host_plan(int64_t n, int32_t n_k, size_t device_bytes, in
  *   T out: complex [n_freq n_bl] rows with leading dimension ldT >= n_eta n_uv
  *   (complex elements); rows are channel-major, columns spectral-mode-major.
  * Asynchronous on `stream`; stream-ordered scratch of n_pix n_uv complex.
- * Errors: EOR_ERR_ARG (sizes < 1, n_freq > 65535, n_bl or n_uv > 65535 x 64,
+ * Errors: EOR_ERR_ARG (sizes < 1, n_freq > 65535, n_bl > 65535 x 32, n_uv > 65535 x 64,
  * n_eta > 2^20, n_pix n_uv > 2^34, NULL array, ldT too small, norm not
  * finite), EOR_ERR_HIP, EOR_ERR_OOM.
  */

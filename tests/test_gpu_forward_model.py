@@ -1,7 +1,8 @@
 """GPU forward model (eor_forward_model) against the FP64 oracle
 (oracle/forward_model.py): element by element on small ragged shapes (pixel
-count not a multiple of the 16-pixel stage, baselines and uv cells not
-multiples of the 64 x 64 tile, a padded leading dimension), the degenerate
+count not a multiple of the 16-pixel stage, baselines not multiples of the
+32-baseline tile and uv cells not multiples of the 128-cell tile, a padded
+leading dimension), the degenerate
 1 x 1 case, sampled entries of the full 20000 x 4096 synthetic instrument,
 and the likelihood of data seen through a forward-modelled T."""
 import numpy as np
