@@ -24,7 +24,8 @@ def _random_instrument(rng, F, n_bl, n_pix, n_uv, n_eta):
     return freq, bl, lm, beam, uv, Z
 
 
-@pytest.mark.parametrize("F,n_bl,n_pix,n_uv,n_eta", [(3, 70, 300, 80, 5), (2, 129, 17, 64, 3), (1, 1, 1, 1, 1)])
+@pytest.mark.parametrize("F,n_bl,n_pix,n_uv,n_eta", [(3, 70, 300, 80, 5), (2, 129, 17, 64, 3), (1, 1, 1, 1, 1),
+                                                   (2, 40, 50, 200, 2)])
 def test_forward_model_matches_oracle(F, n_bl, n_pix, n_uv, n_eta):
     import torch
     import paper_2501_12928_amd as eor
