@@ -547,7 +547,7 @@ def main():
     ap.add_argument("--gated-config", type=int, default=4, help="workload of the gated run (1 or 4)")
     ap.add_argument("--n-live", type=int, default=500)
     ap.add_argument("--first-train", type=int, default=30000)
-    ap.add_argument("--retrain-every", type=int, default=5000)
+    ap.add_argument("--retrain-every", type=int, default=1000)
     ap.add_argument("--window", type=int, default=8000)
     ap.add_argument("--tau", type=float, default=0.05)
     ap.add_argument("--margin", type=float, default=10.0)
