@@ -337,7 +337,8 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
  *            for eor_precompute
  *   theta    host double [B x n_k];  logL host double [B];  info host int32
  *            [B] or NULL (0, -1 for an invalid theta, or the 1-based column of
- *            the first non-positive pivot; logL = -inf then)
+ *            the first non-positive pivot; logL = -inf then); B = 0 returns
+ *            EOR_OK after the argument checks (theta and logL may be NULL)
  *   device_bytes: the device memory the call may use, split evenly between
  *            the lanes; each lane needs one column of tiles twice over (about
  *            2 ceil(n/64) x 64 KiB) plus O(n)

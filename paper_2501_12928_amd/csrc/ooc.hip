@@ -508,7 +508,7 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
                                        int64_t B, const double *theta, size_t device_bytes, int32_t lanes,
                                        double *logL, int32_t *info) {
     using namespace eor;
-    if (n < 1 || n_k < 1 || B < 0 || ldA < n || !A || !dbar || !bin_of || !fixed_var || !theta || !logL)
+    if (n < 1 || n_k < 1 || B < 0 || ldA < n || !A || !dbar || !bin_of || !fixed_var || (B > 0 && (!theta || !logL)))
         return fail_status(EOR_ERR_ARG, "eor_loglike_host: bad sizes or NULL array");
     if (n > ((int64_t)1 << 22)) return fail_status(EOR_ERR_ARG, "eor_loglike_host: n > 2^22");
     for (int64_t d = 0; d < n; ++d) {

@@ -287,3 +287,54 @@ def test_fp64_mfma_probe():
     assert 10.0 < tf <= 80.0 and ms > 0.0, (tf, ms)
     with pytest.raises(eor.EorError):
         eor.probe_fp64_mfma(0)
+
+
+def test_empty_batches(orc):
+    """Zero theta is a valid call everywhere: the batched path, a group with
+    an empty instance beside a full one (and a group call with every
+    instance empty), the surrogate's gate and the out-of-core path."""
+    import torch
+    import paper_2501_12928_amd as eor
+    a = synth.small(seed=81, m=300, n=130, n_k=3, n_theta=5)
+    b = synth.small(seed=82, m=200, n=70, n_k=2, n_theta=4)
+    ctxs = []
+    for inst in (a, b):
+        c = eor.Context(0)
+        c.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                     torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
+        ctxs.append(c)
+    print("gpu: empty batches", flush=True)
+    L, info = ctxs[0].loglike_batch(torch.empty((0, a.n_k), dtype=torch.float64, device="cuda"))
+    assert L.shape == (0,) and info.shape == (0,)
+    lib = eor.lib()
+    assert lib.eor_loglike_batch(ctxs[0]._h, 0, None, None, None, None) == eor.EOR_OK
+    g = eor.Group(ctxs)
+    outs, infos = g.loglike([torch.empty((0, a.n_k), dtype=torch.float64, device="cuda"),
+                             torch.from_numpy(b.theta).cuda()])
+    torch.cuda.synchronize()
+    ref, _ = orc.loglike_instance(b)
+    got = outs[1].cpu().numpy()
+    assert outs[0].shape == (0,) and np.all(infos[1].cpu().numpy() == 0)
+    assert np.all(np.abs(got - ref) <= tol(ref))
+    outs, _ = g.loglike([torch.empty((0, a.n_k), dtype=torch.float64, device="cuda"),
+                         torch.empty((0, b.n_k), dtype=torch.float64, device="cuda")])
+    torch.cuda.synchronize()
+    assert outs[0].shape == (0,) and outs[1].shape == (0,)
+    g.close()
+    s = eor.Surrogate(3, -1.0, 3.0, n_members=2, hidden=16, seed=1)
+    rng = np.random.default_rng(3)
+    th = rng.uniform(-1.0, 3.0, size=(256, 3))
+    s.train(th, -np.sum(th ** 2, axis=1), cfg=eor.train_cfg(epochs=2, minibatch=64))
+    m, sp, dec = s.gate(torch.empty((0, 3), dtype=torch.float64, device="cuda"), 0.0, 0.05)
+    assert m.shape == (0,) and dec.shape == (0,)
+    A, dbar, c, K0 = orc.precompute(a.T, a.noise_var, a.d)
+    got, inf = eor.loglike_host(A, dbar, c, K0, a.n_k, a.bin_of, a.fixed_var, None, np.empty((0, a.n_k)), 1 << 26)
+    assert got.shape == (0,) and inf.shape == (0,)
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    dbar = np.ascontiguousarray(dbar, dtype=np.complex128)
+    bins = np.ascontiguousarray(a.bin_of, dtype=np.int32)
+    fv = np.ascontiguousarray(a.fixed_var, dtype=np.float64)
+    assert lib.eor_loglike_host(0, a.n, A.ctypes.data, a.n, dbar.ctypes.data, c, K0, a.n_k, bins.ctypes.data,
+                                fv.ctypes.data, None, 0, None, 1 << 26, 0, None, None) == eor.EOR_OK
+    for ctx in ctxs:
+        ctx.close()
