@@ -180,10 +180,14 @@ __global__ __launch_bounds__(256) void ooc_pass_kernel(double2 *__restrict__ C, 
 }
 
 // Diagonal tile of column j: Cholesky in LDS, ln det, the inverse of L_jj
-// and y_j = L_jj^-1 w_j. One workgroup. The elimination runs unscaled,
+// and y_j = L_jj^-1 w_j. One workgroup of PT threads, PS per row of the
+// elimination and per column of the inverse. The elimination runs unscaled,
 // S[r][s] -= S[r][c] conj(S[s][c]) / d_c with d_c = S[c][c] (one barrier per
 // column), and L[r][c] = S[r][c] / sqrt(d_c) is formed where it is used.
-__global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0, double2 *__restrict__ Linv,
+constexpr int PT = 512;      // threads of the diagonal factorisation
+constexpr int PS = PT / OT;  // threads per row (elimination) or column (inverse): 8
+
+__global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0, double2 *__restrict__ Linv,
                                                         double2 *__restrict__ w, double2 *__restrict__ y,
                                                         int64_t j, OocState *st) {
     __shared__ double2 S[OT][OT + 1];
@@ -194,13 +198,13 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     if (st->info != 0) return;
     const int tid = threadIdx.x;
     {
-        // all sixteen loads of the thread in flight before the first LDS store
-        double2 v[OT2 / 256];
+        // all of the thread's loads in flight before the first LDS store
+        double2 v[OT2 / PT];
 #pragma unroll
-        for (int u = 0; u < OT2 / 256; ++u) v[u] = C0[tid + 256 * u];
+        for (int u = 0; u < OT2 / PT; ++u) v[u] = C0[tid + PT * u];
 #pragma unroll
-        for (int u = 0; u < OT2 / 256; ++u) {
-            const int e = tid + 256 * u;
+        for (int u = 0; u < OT2 / PT; ++u) {
+            const int e = tid + PT * u;
             S[e / OT][e % OT] = v[u];
             V[e / OT][e % OT] = make_double2(0.0, 0.0);
         }
@@ -208,9 +212,10 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     if (tid == 0) fail_col = 0;
     __syncthreads();
     if (tid < OT) yj[tid] = w[OT * j + tid];  // w_j, read by the solve below
-    // thread (row r = tid / 4, part = tid % 4) updates S[r][s] for s = c+1+part,
-    // c+5+part, ... <= r: the later rows' lower triangle, no index division
-    const int er = tid >> 2, ep = tid & 3;
+    // thread (row r = tid / PS, part = tid % PS) updates S[r][s] for s =
+    // c+1+part, c+1+part+PS, ... <= r: the later rows' lower triangle, no
+    // index division
+    const int er = tid / PS, ep = tid % PS;
     for (int c = 0; c < OT; ++c) {
         const double dcc = S[c][c].x;
         if (!(dcc > 0.0) || !isfinite(dcc)) {
@@ -226,17 +231,17 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
             };
             int s = c + 1 + ep;
             // four updates at a time, their eight LDS reads issued before any write
-            for (; s + 12 <= er; s += 16) {
+            for (; s + 3 * PS <= er; s += 4 * PS) {
                 double2 b[4], x[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    b[u] = S[s + 4 * u][c];
-                    x[u] = S[er][s + 4 * u];
+                    b[u] = S[s + PS * u][c];
+                    x[u] = S[er][s + PS * u];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) S[er][s + 4 * u] = upd(x[u], b[u]);
+                for (int u = 0; u < 4; ++u) S[er][s + PS * u] = upd(x[u], b[u]);
             }
-            for (; s <= er; s += 4) S[er][s] = upd(S[er][s], S[s][c]);
+            for (; s <= er; s += PS) S[er][s] = upd(S[er][s], S[s][c]);
         }
         __syncthreads();
     }
@@ -251,12 +256,12 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
         lsq[tid] = log(sq[tid]);
     }
     __syncthreads();
-    // inverse of the lower factor: four lanes per column (one wave holds
-    // sixteen columns), the sum over t split by t mod 4 and added in a fixed
-    // xor order; lane 0 of the four writes V[r][cc], which the wave's later
+    // inverse of the lower factor: PS lanes per column (one wave holds
+    // 64 / PS columns), the sum over t split by t mod PS and added in a fixed
+    // xor order; lane 0 of the PS writes V[r][cc], which the wave's later
     // LDS reads see in order
     {
-        const int cc = tid >> 2, part = tid & 3;
+        const int cc = tid / PS, part = tid % PS;
         if (part == 0) V[cc][cc] = make_double2(isq[cc], 0.0);
         for (int r = 1; r < OT; ++r) {
             if (r > cc) {
@@ -267,23 +272,24 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
                 };
                 int t = cc + part;
                 // the reads of four terms issued together, the terms added in order
-                for (; t + 12 < r; t += 16) {
+                for (; t + 3 * PS < r; t += 4 * PS) {
                     double2 a[4], b[4];
                     double lt[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        a[u] = S[r][t + 4 * u];
-                        b[u] = V[t + 4 * u][cc];
-                        lt[u] = isq[t + 4 * u];
+                        a[u] = S[r][t + PS * u];
+                        b[u] = V[t + PS * u][cc];
+                        lt[u] = isq[t + PS * u];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) acc(a[u], b[u], lt[u]);
                 }
-                for (; t < r; t += 4) acc(S[r][t], V[t][cc], isq[t]);
-                sr += __shfl_xor(sr, 1);
-                si += __shfl_xor(si, 1);
-                sr += __shfl_xor(sr, 2);
-                si += __shfl_xor(si, 2);
+                for (; t < r; t += PS) acc(S[r][t], V[t][cc], isq[t]);
+#pragma unroll
+                for (int o = 1; o < PS; o <<= 1) {
+                    sr += __shfl_xor(sr, o);
+                    si += __shfl_xor(si, o);
+                }
                 if (part == 0) {
                     const double f = -isq[r];
                     V[r][cc] = make_double2(sr * f, si * f);
@@ -293,7 +299,7 @@ __global__ __launch_bounds__(256) void ooc_potrf_kernel(double2 *__restrict__ C0
     }
     __syncthreads();
     // write L_jj (zero above the diagonal) and its inverse
-    for (int e = tid; e < OT2; e += 256) {
+    for (int e = tid; e < OT2; e += PT) {
         const int r = e / OT, c = e % OT;
         const double2 l = c < r ? make_double2(S[r][c].x * isq[c], S[r][c].y * isq[c])
                                 : (c == r ? make_double2(sq[r], 0.0) : make_double2(0.0, 0.0));
@@ -650,7 +656,7 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
             for (int64_t j = j0; j < j1; ++j) {
                 const int64_t rows = N - j;
                 double2 *Cj = L.C.p + (col_off(j) - col_off(j0)) * OT2;
-                hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(256), 0, s, Cj, L.Linv.p, L.w.p, L.y.p, j, L.st.p);
+                hipLaunchKernelGGL(ooc_potrf_kernel, dim3(1), dim3(PT), 0, s, Cj, L.Linv.p, L.w.p, L.y.p, j, L.st.p);
                 if (rows > 1)
                     hipLaunchKernelGGL(ooc_trsm_kernel, dim3((unsigned)(rows - 1)), dim3(256), 0, s, Cj, L.Linv.p,
                                        L.w.p, L.y.p, j, L.st.p);
