@@ -347,10 +347,11 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
  *            host buffers (lanes + 1 copies of the packed lower triangle)
  *            within half of the host's physical memory
  * The schedule (lanes, pass width) follows from n, n_k, device_bytes and
- * lanes alone, never from B, so a theta's result does not depend on the
- * batch it is in; a different pass width sums the tile products in a
- * different order, so results for different device_bytes or lanes agree to
- * rounding only. Synchronous; allocates its device buffers, a pinned packed
+ * lanes (with lanes = 0, also from the host's memory), never from B, so a
+ * theta's result does not depend on the batch it is in; a different pass
+ * width sums the tile products in a different order, so results for
+ * different device_bytes or lanes agree to rounding only (pass lanes > 0 for
+ * the same bits on hosts of different memory sizes). Synchronous; allocates its device buffers, a pinned packed
  * copy of A and one pinned host factor per lane in use (ceil(n/64)
  * (ceil(n/64) + 1) / 2 tiles each), and frees them before returning.
  * Errors: EOR_ERR_ARG (sizes, NULL arrays, bin_of out of range, fixed
