@@ -180,23 +180,30 @@ __global__ __launch_bounds__(256) void ooc_pass_kernel(double2 *__restrict__ C, 
 }
 
 // Diagonal tile of column j: Cholesky in LDS, ln det, the inverse of L_jj
-// and y_j = L_jj^-1 w_j. One workgroup of PT threads, PS per row of the
-// elimination and per column of the inverse. The elimination runs unscaled,
-// S[r][s] -= S[r][c] conj(S[s][c]) / d_c with d_c = S[c][c] (one barrier per
-// column), and L[r][c] = S[r][c] / sqrt(d_c) is formed where it is used.
-constexpr int PT = 512;      // threads of the diagonal factorisation
-constexpr int PS = PT / OT;  // threads per row (elimination) or column (inverse): 8
+// and y_j = L_jj^-1 w_j. One workgroup of PT threads, blocked on 16 x 16
+// sub-blocks so that few steps wait on a barrier:
+//  - Cholesky, right-looking over the four block columns: one wave factors
+//    the diagonal block (no barrier inside a wave: its LDS accesses run in
+//    program order), one thread per row solves the panel below it, and all
+//    threads apply the rank-16 update to the rest;
+//  - inverse: the four diagonal blocks are inverted at once, one wave each,
+//    then the blocks below them, nearest the diagonal first:
+//    V_ij = -V_ii sum_{k=j..i-1} L_ik V_kj.
+constexpr int PT = 512;  // threads of the diagonal factorisation
+constexpr int PB = 16;   // sub-block size
+constexpr int NPB = OT / PB;
 
 __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0, double2 *__restrict__ Linv,
                                                         double2 *__restrict__ w, double2 *__restrict__ y,
                                                         int64_t j, OocState *st) {
-    __shared__ double2 S[OT][OT + 1];
-    __shared__ double2 V[OT][OT + 1];
-    __shared__ double sq[OT], isq[OT], lsq[OT];
+    __shared__ double2 S[OT][OT + 1];              // C_jj, then L_jj (lower)
+    __shared__ double2 V[OT][OT + 1];              // L_jj^-1 (lower; zero above)
+    __shared__ double2 X[NPB - 1][PB][PB + 1];     // block products of the inverse
+    __shared__ double dinv[OT], lsq[OT];
     __shared__ double2 yj[OT];
     __shared__ int fail_col;
     if (st->info != 0) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     {
         // all of the thread's loads in flight before the first LDS store
         double2 v[OT2 / PT];
@@ -210,106 +217,151 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
         }
     }
     if (tid == 0) fail_col = 0;
-    __syncthreads();
     if (tid < OT) yj[tid] = w[OT * j + tid];  // w_j, read by the solve below
-    // thread (row r = tid / PS, part = tid % PS) updates S[r][s] for s =
-    // c+1+part, c+1+part+PS, ... <= r: the later rows' lower triangle, no
-    // index division
-    const int er = tid / PS, ep = tid % PS;
-    for (int c = 0; c < OT; ++c) {
-        const double dcc = S[c][c].x;
-        if (!(dcc > 0.0) || !isfinite(dcc)) {
-            if (tid == 0) fail_col = c + 1;
-            break;  // uniform: every thread reads the same value
-        }
-        if (er > c) {
-            const double inv = 1.0 / dcc;
-            const double2 a = S[er][c];
-            const double ar = a.x * inv, ai = a.y * inv;
-            auto upd = [&](double2 x, double2 b) {
-                return make_double2(x.x - (ar * b.x + ai * b.y), x.y - (ai * b.x - ar * b.y));
-            };
-            int s = c + 1 + ep;
-            // four updates at a time, their eight LDS reads issued before any write
-            for (; s + 3 * PS <= er; s += 4 * PS) {
-                double2 b[4], x[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    b[u] = S[s + PS * u][c];
-                    x[u] = S[er][s + PS * u];
+    __syncthreads();
+
+    for (int kb = 0; kb < NPB; ++kb) {
+        const int b0 = PB * kb, r0 = b0 + PB;
+        // diagonal block, by wave 0: lane (r = lane / 4, s = lane % 4 + 4 u)
+        if (wv == 0) {
+            const int br = lane >> 2, bs = lane & 3;
+            for (int c = 0; c < PB; ++c) {
+                const double d = S[b0 + c][b0 + c].x;
+                if (!(d > 0.0) || !isfinite(d)) {
+                    if (lane == 0) fail_col = b0 + c + 1;
+                    break;  // uniform: every lane of the wave reads the same value
                 }
+                const double l = sqrt(d), il = 1.0 / l;
+                if (bs == 0 && br > c) {
+                    const double2 x = S[b0 + br][b0 + c];
+                    S[b0 + br][b0 + c] = make_double2(x.x * il, x.y * il);
+                }
+                if (lane == 0) S[b0 + c][b0 + c] = make_double2(l, 0.0);
+                if (br > c) {
+                    const double2 a = S[b0 + br][b0 + c];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) S[er][s + PS * u] = upd(x[u], b[u]);
+                    for (int u = 0; u < PB / 4; ++u) {
+                        const int sc = bs + 4 * u;
+                        if (sc > c && sc <= br) {
+                            const double2 b = S[b0 + sc][b0 + c];
+                            const double2 x = S[b0 + br][b0 + sc];
+                            // x - a conj(b)
+                            S[b0 + br][b0 + sc] = make_double2(x.x - (a.x * b.x + a.y * b.y),
+                                                               x.y - (a.y * b.x - a.x * b.y));
+                        }
+                    }
+                }
             }
-            for (; s <= er; s += PS) S[er][s] = upd(S[er][s], S[s][c]);
         }
         __syncthreads();
+        if (fail_col != 0) break;  // uniform: read after the barrier
+        if (r0 < OT) {
+            // panel below: row r solves x L_kk^H = s, one thread per row
+            if (tid < OT - r0) {
+                const int r = r0 + tid;
+                double2 x[PB];
+#pragma unroll
+                for (int c = 0; c < PB; ++c) {
+                    double2 a = S[r][b0 + c];
+#pragma unroll
+                    for (int t = 0; t < c; ++t) {
+                        const double2 l = S[b0 + c][b0 + t];  // x_t conj(l)
+                        a.x -= x[t].x * l.x + x[t].y * l.y;
+                        a.y -= x[t].y * l.x - x[t].x * l.y;
+                    }
+                    const double il = 1.0 / S[b0 + c][b0 + c].x;
+                    x[c] = make_double2(a.x * il, a.y * il);
+                }
+#pragma unroll
+                for (int c = 0; c < PB; ++c) S[r][b0 + c] = x[c];
+            }
+            __syncthreads();
+            // rank-16 update of the rest: S[r][s] -= sum_t L[r][t] conj(L[s][t]), r0 <= s <= r
+#pragma unroll
+            for (int u = 0; u < OT2 / PT; ++u) {
+                const int e = tid + PT * u, r = e >> 6, sc = e & 63;
+                if (sc >= r0 && sc <= r) {
+                    double2 acc = S[r][sc];
+#pragma unroll
+                    for (int t = 0; t < PB; ++t) {
+                        const double2 a = S[r][b0 + t], b = S[sc][b0 + t];
+                        acc.x -= a.x * b.x + a.y * b.y;
+                        acc.y -= a.y * b.x - a.x * b.y;
+                    }
+                    S[r][sc] = acc;
+                }
+            }
+            __syncthreads();
+        }
     }
-    __syncthreads();
     if (fail_col != 0) {
         if (tid == 0) st->info = (int32_t)(OT * j + fail_col);
         return;
     }
     if (tid < OT) {
-        sq[tid] = sqrt(S[tid][tid].x);
-        isq[tid] = 1.0 / sq[tid];
-        lsq[tid] = log(sq[tid]);
+        const double l = S[tid][tid].x;
+        dinv[tid] = 1.0 / l;
+        lsq[tid] = log(l);
     }
     __syncthreads();
-    // inverse of the lower factor: PS lanes per column (one wave holds
-    // 64 / PS columns), the sum over t split by t mod PS and added in a fixed
-    // xor order; lane 0 of the PS writes V[r][cc], which the wave's later
-    // LDS reads see in order
-    {
-        const int cc = tid / PS, part = tid % PS;
-        if (part == 0) V[cc][cc] = make_double2(isq[cc], 0.0);
-        for (int r = 1; r < OT; ++r) {
+    // inverse: diagonal blocks, wave kb on block kb, lane = column
+    if (wv < NPB && lane < PB) {
+        const int b0 = PB * wv, cc = lane;
+        V[b0 + cc][b0 + cc] = make_double2(dinv[b0 + cc], 0.0);
+        for (int r = 1; r < PB; ++r) {
             if (r > cc) {
                 double sr = 0.0, si = 0.0;
-                auto acc = [&](double2 a, double2 b, double lt) {
-                    sr += (a.x * b.x - a.y * b.y) * lt;
-                    si += (a.x * b.y + a.y * b.x) * lt;
-                };
-                int t = cc + part;
-                // the reads of four terms issued together, the terms added in order
-                for (; t + 3 * PS < r; t += 4 * PS) {
-                    double2 a[4], b[4];
-                    double lt[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        a[u] = S[r][t + PS * u];
-                        b[u] = V[t + PS * u][cc];
-                        lt[u] = isq[t + PS * u];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc(a[u], b[u], lt[u]);
+#pragma unroll 4
+                for (int t = cc; t < r; ++t) {
+                    const double2 a = S[b0 + r][b0 + t], b = V[b0 + t][b0 + cc];
+                    sr += a.x * b.x - a.y * b.y;
+                    si += a.x * b.y + a.y * b.x;
                 }
-                for (; t < r; t += PS) acc(S[r][t], V[t][cc], isq[t]);
-#pragma unroll
-                for (int o = 1; o < PS; o <<= 1) {
-                    sr += __shfl_xor(sr, o);
-                    si += __shfl_xor(si, o);
-                }
-                if (part == 0) {
-                    const double f = -isq[r];
-                    V[r][cc] = make_double2(sr * f, si * f);
-                }
+                const double f = -dinv[b0 + r];
+                V[b0 + r][b0 + cc] = make_double2(sr * f, si * f);
             }
         }
     }
     __syncthreads();
+    // blocks below the diagonal, distance dd = i - jb: X = sum_k L_ik V_k,jb, then V_i,jb = -V_ii X
+    for (int dd = 1; dd < NPB; ++dd) {
+        const int nblk = NPB - dd;
+        for (int e = tid; e < nblk * PB * PB; e += PT) {
+            const int jb = e >> 8, a = (e >> 4) & 15, b = e & 15, ib = jb + dd;
+            double sr = 0.0, si = 0.0;
+#pragma unroll 4
+            for (int k = PB * jb; k < PB * ib; ++k) {
+                const double2 l = S[PB * ib + a][k], v = V[k][PB * jb + b];
+                sr += l.x * v.x - l.y * v.y;
+                si += l.x * v.y + l.y * v.x;
+            }
+            X[jb][a][b] = make_double2(sr, si);
+        }
+        __syncthreads();
+        for (int e = tid; e < nblk * PB * PB; e += PT) {
+            const int jb = e >> 8, a = (e >> 4) & 15, b = e & 15, ib = jb + dd;
+            double sr = 0.0, si = 0.0;
+#pragma unroll 4
+            for (int t = 0; t <= a; ++t) {
+                const double2 v = V[PB * ib + a][PB * ib + t], x = X[jb][t][b];
+                sr += v.x * x.x - v.y * x.y;
+                si += v.x * x.y + v.y * x.x;
+            }
+            V[PB * ib + a][PB * jb + b] = make_double2(-sr, -si);
+        }
+        __syncthreads();
+    }
     // write L_jj (zero above the diagonal) and its inverse
     for (int e = tid; e < OT2; e += PT) {
         const int r = e / OT, c = e % OT;
-        const double2 l = c < r ? make_double2(S[r][c].x * isq[c], S[r][c].y * isq[c])
-                                : (c == r ? make_double2(sq[r], 0.0) : make_double2(0.0, 0.0));
-        C0[e] = l;
+        C0[e] = c < r ? S[r][c] : (c == r ? make_double2(S[r][r].x, 0.0) : make_double2(0.0, 0.0));
         Linv[e] = c <= r ? V[r][c] : make_double2(0.0, 0.0);
     }
     // y_j = Linv w_j (w_j in yj since the start; every thread reads it before
     // the rows' results replace it)
     double sr = 0.0, si = 0.0;
     if (tid < OT) {
+#pragma unroll 4
         for (int t = 0; t <= tid; ++t) {
             const double2 a = V[tid][t], b = yj[t];
             sr += a.x * b.x - a.y * b.y;
