@@ -127,3 +127,10 @@ def test_ooc_failure_paths(orc):
     got2, info2 = eor.loglike_host(A2, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, None, inst.theta[:1],
                                    1 << 28)
     assert info2[0] == 70 and got2[0] == -np.inf
+    # the same in the third 16-column sub-block of the second tile (1-based column 105),
+    # reached after two rank-16 updates inside the diagonal factorisation
+    A3 = A.copy()
+    A3[104, 104] = -1e12
+    got3, info3 = eor.loglike_host(A3, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, None, inst.theta[:2],
+                                   1 << 28)
+    assert np.all(info3 == 105) and np.all(got3 == -np.inf)
