@@ -154,7 +154,7 @@ def precision_report(ctx, inst, T, nv, d, theta, logL64):
     rep = {"fp64_precompute_ms": timed_pre("fp64")}
     A64 = ctx.export_precompute()[0]
     nrm = torch.linalg.norm(A64).item()
-    for prec in ("fp32", "bf16x3"):
+    for prec in ("fp32", "bf16x3", "bf16x2"):
         ms = timed_pre(prec)
         A = ctx.export_precompute()[0]
         rel = (torch.linalg.norm(A - A64).item()) / nrm

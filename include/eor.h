@@ -57,9 +57,12 @@ typedef enum {
     EOR_PREC_FP64 = 0,    /* A formed in FP64 on FP64 MFMA */
     EOR_PREC_FP32 = 1,    /* W = T/sigma rounded to complex64, FP32 MFMA, FP32
                              accumulation per k-chunk, chunks summed in FP64 */
-    EOR_PREC_BF16X3 = 2   /* W split into three bf16 terms, the six leading
+    EOR_PREC_BF16X3 = 2,  /* W split into three bf16 terms, the six leading
                              cross products on bf16 MFMA with FP32
                              accumulation per k-chunk, chunks summed in FP64 */
+    EOR_PREC_BF16X2 = 3   /* the cheaper split: two bf16 terms and the three
+                             leading cross products (about 2^-16 relative per
+                             product instead of 2^-24), otherwise as BF16X3 */
 } eor_precision;
 
 /* Message of the last failed call on this thread ("" if none). */

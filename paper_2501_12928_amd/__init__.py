@@ -24,7 +24,7 @@ EOR_ERR_OOM = -2
 EOR_ERR_HIP = -3
 EOR_ERR_STATE = -4
 
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
 
 _lib = None
 _P = ctypes.c_void_p

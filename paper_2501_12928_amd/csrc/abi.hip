@@ -199,7 +199,7 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     if (ldT > ((int64_t)1 << 24)) return fail(EOR_ERR_ARG, "eor_precompute: ldT > 2^24");
     if (!T || !noise_var || !d || !bin_of) return fail(EOR_ERR_ARG, "eor_precompute: NULL array");
     if (n_k < 0 || n_k > 4096) return fail(EOR_ERR_ARG, "eor_precompute: need 0 <= n_k <= 4096");
-    if (prec != EOR_PREC_FP64 && prec != EOR_PREC_FP32 && prec != EOR_PREC_BF16X3)
+    if (prec != EOR_PREC_FP64 && prec != EOR_PREC_FP32 && prec != EOR_PREC_BF16X3 && prec != EOR_PREC_BF16X2)
         return fail(EOR_ERR_ARG, "eor_precompute: unknown precision");
     // host-side bin map and constants
     std::vector<int32_t> cnt(n_k > 0 ? n_k : 1, 0);
@@ -310,8 +310,10 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
         EOR_TRY(eor::launch_precompute_fp64(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (fp64)");
     else if (prec == EOR_PREC_FP32)
         EOR_TRY(eor::launch_precompute_fp32(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (fp32)");
+    else if (prec == EOR_PREC_BF16X3)
+        EOR_TRY(eor::launch_precompute_bf16(c, Td, ldT, c.invvar, c.lowp, 3, s), "precompute A (bf16x3)");
     else
-        EOR_TRY(eor::launch_precompute_bf16x3(c, Td, ldT, c.invvar, c.lowp, s), "precompute A (bf16x3)");
+        EOR_TRY(eor::launch_precompute_bf16(c, Td, ldT, c.invvar, c.lowp, 2, s), "precompute A (bf16x2)");
 #undef EOR_TRY
     c.ready = true;
     return EOR_OK;

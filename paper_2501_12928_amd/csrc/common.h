@@ -138,8 +138,8 @@ hipError_t launch_precompute_fp64(const Context &c, const double2 *T, int64_t ld
 size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad, int num_cu);
 hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ldT,
                                   const double *invvar, void *scratch, hipStream_t s);
-hipError_t launch_precompute_bf16x3(const Context &c, const double2 *T, int64_t ldT,
-                                    const double *invvar, void *scratch, hipStream_t s);
+hipError_t launch_precompute_bf16(const Context &c, const double2 *T, int64_t ldT,
+                                  const double *invvar, void *scratch, int nterm, hipStream_t s);
 hipError_t launch_precompute_vectors(const Context &c, const double2 *T, int64_t ldT,
                                      const double *noise_var, const double2 *d, double *invvar,
                                      double2 *partial, int splits, hipStream_t s);

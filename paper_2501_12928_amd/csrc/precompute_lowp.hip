@@ -9,6 +9,8 @@
 //   below 2^-24 |x|); a real product x y keeps the six leading cross products
 //   hh' + hm' + mh' + hl' + mm' + lh' on BF16 MFMA (16x16x32) with FP32
 //   accumulation, and again the 64-row chunk partials go to FP64.
+// BF16x2: the cheaper split into two terms x = h + l (a remainder below
+//   2^-16 |x|) and the three leading products hh' + hl' + lh'.
 //
 // Both MFMAs return D[4(l/16) + r][l%16] in register r (FP32 16x16x4 and
 // BF16 16x16x32), with the A operand lane l = A[l%16][k-group l/16] and the B
@@ -213,11 +215,12 @@ __device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float
 // P[p][j][s] for s < m_pad (zero in the padding), so eight consecutive rows
 // s of one column are 16 contiguous bytes. One block transposes a 64 x 64
 // tile of W through LDS.
+template <int NTERM>
 __global__ __launch_bounds__(256) void split_kernel(const double2 *__restrict__ T, int64_t ldT,
                                                     int64_t m, int64_t n,
                                                     const double *__restrict__ invvar, int64_t m_pad,
                                                     int64_t n_pad, unsigned short *__restrict__ P) {
-    __shared__ unsigned short sh[6][64][65];
+    __shared__ unsigned short sh[2 * NTERM][64][65];
     const int64_t s0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int rr = ty; rr < 64; rr += 4) {
@@ -232,15 +235,14 @@ __global__ __launch_bounds__(256) void split_kernel(const double2 *__restrict__ 
         const float xs[2] = {xr, xi};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const float x = xs[c];
-            const unsigned short h = bf16_bits(x);
-            const float r1 = x - bf16_to_float(h);
-            const unsigned short mm = bf16_bits(r1);
-            const float r2 = r1 - bf16_to_float(mm);
-            const unsigned short l = bf16_bits(r2);
-            sh[3 * c + 0][tx][rr] = h;
-            sh[3 * c + 1][tx][rr] = mm;
-            sh[3 * c + 2][tx][rr] = l;
+            // each term is the bfloat16 nearest what the earlier ones leave
+            float x = xs[c];
+#pragma unroll
+            for (int k = 0; k < NTERM; ++k) {
+                const unsigned short b = bf16_bits(x);
+                sh[NTERM * c + k][tx][rr] = b;
+                x = x - bf16_to_float(b);
+            }
         }
     }
     __syncthreads();
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(256) void split_kernel(const double2 *__restrict__ 
         const int64_t j = j0 + cc, s = s0 + tx;
         if (j < n_pad && s < m_pad) {
 #pragma unroll
-            for (int p = 0; p < 6; ++p) P[((int64_t)p * n_pad + j) * m_pad + s] = sh[p][cc][tx];
+            for (int p = 0; p < 2 * NTERM; ++p) P[((int64_t)p * n_pad + j) * m_pad + s] = sh[p][cc][tx];
         }
     }
 }
@@ -264,39 +266,57 @@ __device__ inline bf8 neg_bf8(bf8 x) {
     return __builtin_bit_cast(bf8, v);
 }
 
-// x y with x = xh + xm + xl, y = yh + ym + yl: the six leading products,
-// smallest first, term e being x[P6X[e]] y[P6Y[e]].
-constexpr int P6X[6] = {2, 1, 0, 1, 0, 0};
-constexpr int P6Y[6] = {0, 1, 2, 0, 1, 0};
+// The leading products of x y with x and y split into NTERM bfloat16 terms,
+// smallest first, term e being x[X[e]] y[Y[e]]: with three terms
+// (h, m, l) the six of order at most 2^-16, with two (h, l) the three of
+// order at most 2^-8.
+template <int NTERM>
+struct Prods;
+template <>
+struct Prods<3> {
+    static constexpr int N = 6;
+    static constexpr int X[6] = {2, 1, 0, 1, 0, 0};
+    static constexpr int Y[6] = {0, 1, 2, 0, 1, 0};
+};
+template <>
+struct Prods<2> {
+    static constexpr int N = 3;
+    static constexpr int X[3] = {1, 0, 0};
+    static constexpr int Y[3] = {0, 1, 0};
+};
 
 // One workgroup per 64 x 64 tile; per step of 32 rows the workgroup copies
-// both 64-column panels (six planes each, 48 KiB) from HBM into LDS once,
+// both 64-column panels (2 NTERM planes each: 48 KiB for three terms) from
+// HBM into LDS once,
 // and every wave reads its operands there (each wave needs its own 16
 // columns of the row panel and all 64 of the column panel, so reading them
 // straight from memory fetched the column panel four times). Two LDS
 // buffers: the next step's panels are read into registers while this
 // step's are multiplied, and stored after it.
-constexpr int BF_COL = 40;                           // LDS stride of a column: 32 rows + 8 pad (bf16)
-constexpr int BF_PANEL = 6 * 64 * BF_COL;            // one panel, six planes
-constexpr int BF_LOADS = 2 * 6 * 64 * 4 / 256;       // 16-byte reads per thread per step (12)
+constexpr int BF_COL = 40;  // LDS stride of a column: 32 rows + 8 pad (bf16)
 
-__global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *__restrict__ P,
-                                                          int64_t m_pad, int64_t n_pad, int64_t n,
-                                                          double2 *__restrict__ Ap) {
+template <int NTERM>
+__global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__restrict__ P,
+                                                        int64_t m_pad, int64_t n_pad, int64_t n,
+                                                        double2 *__restrict__ Ap) {
+    constexpr int NP = 2 * NTERM;                     // planes: NTERM real, NTERM imaginary
+    constexpr int BF_PANEL = NP * 64 * BF_COL;        // one panel, all planes
+    constexpr int BF_LOADS = 2 * NP * 64 * 4 / 256;   // 16-byte reads per thread per step (12 or 8)
+    using PR = Prods<NTERM>;
     __shared__ __align__(16) unsigned short lds[2][2 * BF_PANEL];
     int64_t ti, tj;
     tile_of(blockIdx.x, ti, tj);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
     const int64_t plane = n_pad * m_pad;
     // the thread's share of a step: 16 bytes (8 rows) of one column of one
-    // plane of one panel; e = ((panel * 6 + p) * 64 + col) * 4 + 8-row group
+    // plane of one panel; e = ((panel * NP + p) * 64 + col) * 4 + 8-row group
     const unsigned short *src[BF_LOADS];
     int dst[BF_LOADS];
 #pragma unroll
     for (int u = 0; u < BF_LOADS; ++u) {
         const int e = tid + 256 * u;
-        const int g8 = e & 3, col = (e >> 2) & 63, pp = e >> 8;  // pp = panel * 6 + plane
-        const int panel = pp / 6, p = pp % 6;
+        const int g8 = e & 3, col = (e >> 2) & 63, pp = e >> 8;  // pp = panel * NP + plane
+        const int panel = pp / NP, p = pp % NP;
         const int64_t gcol = TS * (panel == 0 ? ti : tj) + col;
         src[u] = P + (int64_t)p * plane + gcol * m_pad + 8 * g8;
         dst[u] = panel * BF_PANEL + (p * 64 + col) * BF_COL + 8 * g8;
@@ -335,11 +355,11 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
         for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 32) {
             const bool more = s0 + 32 < m_pad;
             if (more) fetch(s0 + 32);
-            bf8 ar[3], ai[3], nai[3];
+            bf8 ar[NTERM], ai[NTERM], nai[NTERM];
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
+            for (int t = 0; t < NTERM; ++t) {
                 ar[t] = opnd(buf, 0, t, 16 * w + l16);
-                ai[t] = opnd(buf, 0, 3 + t, 16 * w + l16);
+                ai[t] = opnd(buf, 0, NTERM + t, 16 * w + l16);
                 nai[t] = neg_bf8(ai[t]);
             }
             // re: br ar + bi ai;  im: bi ar - br ai. Two 16-column blocks at a
@@ -348,27 +368,27 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(const unsigned short *
             // still takes its twelve products in the same order
 #pragma unroll
             for (int cp = 0; cp < 4; cp += 2) {
-                bf8 br[2][3], bi[2][3];
+                bf8 br[2][NTERM], bi[2][NTERM];
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int t = 0; t < 3; ++t) {
+                    for (int t = 0; t < NTERM; ++t) {
                         br[h][t] = opnd(buf, 1, t, 16 * (cp + h) + l16);
-                        bi[h][t] = opnd(buf, 1, 3 + t, 16 * (cp + h) + l16);
+                        bi[h][t] = opnd(buf, 1, NTERM + t, 16 * (cp + h) + l16);
                     }
 #pragma unroll
-                for (int e = 0; e < 6; ++e)
+                for (int e = 0; e < PR::N; ++e)
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        aR[cp + h] = mfma_bf16(br[h][P6X[e]], ar[P6Y[e]], aR[cp + h]);
-                        aI[cp + h] = mfma_bf16(bi[h][P6X[e]], ar[P6Y[e]], aI[cp + h]);
+                        aR[cp + h] = mfma_bf16(br[h][PR::X[e]], ar[PR::Y[e]], aR[cp + h]);
+                        aI[cp + h] = mfma_bf16(bi[h][PR::X[e]], ar[PR::Y[e]], aI[cp + h]);
                     }
 #pragma unroll
-                for (int e = 0; e < 6; ++e)
+                for (int e = 0; e < PR::N; ++e)
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        aR[cp + h] = mfma_bf16(bi[h][P6X[e]], ai[P6Y[e]], aR[cp + h]);
-                        aI[cp + h] = mfma_bf16(br[h][P6X[e]], nai[P6Y[e]], aI[cp + h]);
+                        aR[cp + h] = mfma_bf16(bi[h][PR::X[e]], ai[PR::Y[e]], aR[cp + h]);
+                        aI[cp + h] = mfma_bf16(br[h][PR::X[e]], nai[PR::Y[e]], aI[cp + h]);
                     }
             }
             if (more) stash(buf ^ 1);
@@ -404,6 +424,7 @@ size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad, int num_
         return (size_t)m_pad * n_pad * sizeof(float2) + part;
     }
     if (prec == EOR_PREC_BF16X3) return (size_t)6 * m_pad * n_pad * sizeof(unsigned short);
+    if (prec == EOR_PREC_BF16X2) return (size_t)4 * m_pad * n_pad * sizeof(unsigned short);
     return 0;
 }
 
@@ -425,14 +446,19 @@ hipError_t launch_precompute_fp32(const Context &c, const double2 *T, int64_t ld
     return hipGetLastError();
 }
 
-hipError_t launch_precompute_bf16x3(const Context &c, const double2 *T, int64_t ldT, const double *invvar,
-                                    void *scratch, hipStream_t s) {
+hipError_t launch_precompute_bf16(const Context &c, const double2 *T, int64_t ldT, const double *invvar,
+                                  void *scratch, int nterm, hipStream_t s) {
     const int64_t m_pad = (c.m + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
     unsigned short *P = (unsigned short *)scratch;
-    hipLaunchKernelGGL(split_kernel, dim3((unsigned)(c.n_pad / 64), (unsigned)(m_pad / 64)), dim3(256), 0, s,
-                       T, ldT, c.m, c.n, invvar, m_pad, c.n_pad, P);
-    hipLaunchKernelGGL(herk_bf16x3_kernel, dim3((unsigned)n_tiles(c.N)), dim3(256), 0, s, P, m_pad, c.n_pad,
-                       c.n, c.A);
+    const dim3 sgrid((unsigned)(c.n_pad / 64), (unsigned)(m_pad / 64));
+    const dim3 hgrid((unsigned)n_tiles(c.N));
+    if (nterm == 3) {
+        hipLaunchKernelGGL(split_kernel<3>, sgrid, dim3(256), 0, s, T, ldT, c.m, c.n, invvar, m_pad, c.n_pad, P);
+        hipLaunchKernelGGL(herk_bf16_kernel<3>, hgrid, dim3(256), 0, s, P, m_pad, c.n_pad, c.n, c.A);
+    } else {
+        hipLaunchKernelGGL(split_kernel<2>, sgrid, dim3(256), 0, s, T, ldT, c.m, c.n, invvar, m_pad, c.n_pad, P);
+        hipLaunchKernelGGL(herk_bf16_kernel<2>, hgrid, dim3(256), 0, s, P, m_pad, c.n_pad, c.n, c.A);
+    }
     return hipGetLastError();
 }
 
