@@ -31,10 +31,21 @@
  *    Numerical failures are reported per theta through `info` and never stop
  *    the batch. Nothing throws or aborts across the ABI.
  *  - A context is not thread-safe: use one per host thread.
+ *  - Every call on one handle (context, group or surrogate) uses the handle's
+ *    device buffers (A, the task counter, the per-theta workspace, the
+ *    activations). Calls on one handle may go to different streams: a call
+ *    on a stream other than the previous call's first makes its stream wait
+ *    for the previous call's work (hipStreamWaitEvent), and a call that
+ *    reallocates or rewrites such a buffer first waits on the host until the
+ *    previous call's work has finished. The calls of one handle therefore
+ *    run one after another whatever their streams; work meant to overlap
+ *    needs one handle per stream. A group call also waits for, and is then
+ *    waited for by, the last call on each of its contexts.
  */
 #ifndef EOR_H
 #define EOR_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -142,6 +153,23 @@ eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *d
 
 /* Problem sizes of a context after eor_precompute: m, n, n_k (any may be NULL). */
 eor_status eor_shape(const eor_ctx *ctx, int64_t *m, int64_t *n, int32_t *n_k);
+
+/*
+ * Device-memory budget of the per-theta workspace of eor_loglike_batch and
+ * eor_loglike_terms ("Running BayesEoR" sizes an analysis by the memory it
+ * needs; this bounds what the batched likelihood adds to it). Each theta
+ * in flight needs one slot of 16 n_pad^2 / 2 + 16 n_pad bytes, n_pad = n
+ * rounded up to 64 (the packed tiles of L and the solve vector): about 136 MB
+ * at n = 4096. With a budget, a call keeps at most floor(bytes / slot) theta
+ * in flight (fewer workgroups, the same results); a budget below one slot
+ * makes the next call return EOR_ERR_OOM before any launch.
+ *   bytes  0 = no budget (the default: one slot per resident workgroup, as
+ *          many as the device holds)
+ * A workspace already allocated beyond the new budget is freed once the
+ * context's queued work has finished. Errors: EOR_ERR_ARG (NULL ctx),
+ * EOR_ERR_HIP.
+ */
+eor_status eor_set_workspace_limit(eor_ctx *ctx, size_t bytes);
 
 /*
  * Launch choices of this context's eor_loglike_batch / eor_loglike_terms

@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
         L.eor_group_set_tuning.argtypes = [_P, _I32, _I32, _I32]
         L.eor_set_tuning.argtypes = [_P, _I32, _I32, _I32]
+        L.eor_set_workspace_limit.argtypes = [_P, ctypes.c_size_t]
         L.eor_get_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]
         L.eor_autotune.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.c_char_p, _I32, _P]
         L.eor_surrogate_create.argtypes = [ctypes.c_int, _I32, _I32, _I32, ctypes.c_uint64, _P, _P,
@@ -104,6 +105,7 @@ def lib() -> ctypes.CDLL:
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
                      "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
                      "eor_group_set_graph", "eor_group_tuning", "eor_group_set_tuning", "eor_set_tuning",
+                     "eor_set_workspace_limit",
                      "eor_get_tuning", "eor_autotune", "eor_surrogate_create",
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
@@ -209,6 +211,11 @@ class Context:
     def set_tuning(self, stages, wg_per_cu, tiles_per_pass=1):
         """Launch choices of loglike_batch / loglike_terms (see eor_set_tuning)."""
         check(lib().eor_set_tuning(self._h, stages, wg_per_cu, tiles_per_pass))
+
+    def set_workspace_limit(self, nbytes: int):
+        """Device-memory budget of the per-theta workspace (0 = none); see
+        eor_set_workspace_limit."""
+        check(lib().eor_set_workspace_limit(self._h, int(nbytes)))
 
     def tuning(self):
         """(prefetch stages, workgroups per CU, tiles per pass)."""

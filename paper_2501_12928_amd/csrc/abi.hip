@@ -120,6 +120,9 @@ struct DeviceGuard {
 // Make sure there is workspace for `want` resident workgroups.
 eor_status ensure_work(Context &c, int64_t want) {
     if (c.slots >= want) return EOR_OK;
+    // queued work may still use the current slots
+    const hipError_t ed = c.order.drain();
+    if (ed != hipSuccess) return hip_fail(ed, "hipEventSynchronize");
     free_work(c);
     const int64_t slot_tiles = eor::n_tiles(c.N);
     const size_t per_slot = (size_t)slot_tiles * eor::TS2 * sizeof(double2) + (size_t)c.n_pad * sizeof(double2);
@@ -185,6 +188,7 @@ void eor_destroy(eor_ctx *ctx) {
     (void)hipDeviceSynchronize();
     free_problem(ctx->c);
     free_work(ctx->c);
+    ctx->c.order.destroy();
     delete ctx;
 }
 
@@ -225,9 +229,11 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     Context &c = ctx->c;
     DeviceGuard g(c.device);
     hipStream_t s = (hipStream_t)stream;
-    // Queued work may still read the previous problem's arrays and the
-    // pinned staging buffers.
-    hipError_t e = hipStreamSynchronize(s);
+    // Queued work, on this stream or on the stream of the context's (or a
+    // group's) last call, may still read the previous problem's arrays and
+    // the pinned staging buffers.
+    hipError_t e = c.order.drain();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     const int64_t N = (n + eor::TS - 1) / eor::TS;
     if (c.alloc_m != m || c.alloc_n != n || c.alloc_k != n_k) {
@@ -315,6 +321,8 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     else
         EOR_TRY(eor::launch_precompute_bf16(c, Td, ldT, c.invvar, c.lowp, 2, s), "precompute A (bf16x2)");
 #undef EOR_TRY
+    e = c.order.leave(s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     c.ready = true;
     return EOR_OK;
 }
@@ -344,8 +352,13 @@ static eor_status loglike_impl(eor_ctx *ctx, int64_t B, const double *theta, dou
     p.slot_y = c.slot_y;
     p.call[0] = eor::CallDesc{theta, logL, info, terms};
     const int64_t grid = want < c.slots ? want : c.slots;
-    hipError_t e = eor::launch_likelihood(p, c.tune, grid, (hipStream_t)stream);
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = c.order.enter(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    e = eor::launch_likelihood(p, c.tune, grid, s);
     if (e != hipSuccess) return hip_fail(e, "likelihood launch");
+    e = c.order.leave(s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     return EOR_OK;
 }
 
@@ -368,7 +381,8 @@ eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *d
     if (A_out && ldA < c.n) return fail(EOR_ERR_ARG, "eor_export_precompute: ldA < n");
     DeviceGuard g(c.device);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
+    hipError_t e = c.order.enter(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     if (A_out) {
         e = eor::launch_export_A(c, (double2 *)A_out, ldA, s);
         if (e != hipSuccess) return hip_fail(e, "export A");
@@ -385,6 +399,26 @@ eor_status eor_export_precompute(eor_ctx *ctx, void *A_out, int64_t ldA, void *d
         scalars[0] = sc[0];
         scalars[1] = c.khost + sc[1];
     }
+    e = c.order.leave(s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return EOR_OK;
+}
+
+eor_status eor_set_workspace_limit(eor_ctx *ctx, size_t bytes) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_set_workspace_limit: ctx is NULL");
+    Context &c = ctx->c;
+    DeviceGuard g(c.device);
+    if (c.slots > 0) {
+        const size_t per_slot = (size_t)c.slot_tiles * eor::TS2 * sizeof(double2) + (size_t)c.slot_y * sizeof(double2);
+        if (bytes > 0 && (size_t)c.slots * per_slot > bytes) {
+            // the current workspace is over the new limit: free it once the
+            // work that uses it has finished; the next call allocates anew
+            const hipError_t e = c.order.drain();
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            free_work(c);
+        }
+    }
+    c.work_limit = bytes;
     return EOR_OK;
 }
 

@@ -68,6 +68,42 @@ struct LikeParams {
     CallDesc call[MAX_INST];
 };
 
+// Orders the calls on one handle across streams. A handle's device buffers
+// (task counter, workspace slots, A and the tables, surrogate activations)
+// are shared by all of its calls, so a call issued on a stream other than the
+// previous call's first makes its stream wait for the previous call's work,
+// and a call that rewrites what queued work may still read first waits on the
+// host. Calls on one stream are ordered by the stream itself.
+struct StreamOrder {
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;
+    bool pending = false;
+    // Before the call's first device work on s.
+    hipError_t enter(hipStream_t s) const {
+        return (pending && s != last) ? hipStreamWaitEvent(s, ev, 0) : hipSuccess;
+    }
+    // After the call's last device work on s.
+    hipError_t leave(hipStream_t s) {
+        if (!ev) {
+            const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = hipEventRecord(ev, s);
+        if (e == hipSuccess) {
+            last = s;
+            pending = true;
+        }
+        return e;
+    }
+    // Block the host until the previous call's device work has finished.
+    hipError_t drain() const { return pending ? hipEventSynchronize(ev) : hipSuccess; }
+    void destroy() {
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+        pending = false;
+    }
+};
+
 // Launch choices the autotuner picks between.
 struct Tuning {
     int stages = 4;      // register prefetch depth of the panel update (2 or 4)
@@ -117,6 +153,7 @@ struct Context {
     int64_t slot_tiles = 0;      // tiles per slot
     int64_t slot_y = 0;          // complex entries of y per slot
     size_t work_limit = 0;       // bytes; 0 = no limit
+    StreamOrder order;           // the last call's work on its stream
 };
 
 // Shared helpers of the ABI layer (abi.hip).

@@ -88,8 +88,10 @@ __device__ inline T *uniform_ptr(T *p) {
     return (T *)(((uint64_t)hi << 32) | lo);
 }
 
-// Raw buffer over nbytes at p (a wave-uniform address). Loads past nbytes
-// return zero.
+// Raw buffer over nbytes at p (a wave-uniform address). A load whose vector
+// offset (plus instruction offset) is not below nbytes returns zero and
+// touches no memory; the scalar offset is not part of that range check, so
+// every load keeps its scalar offset inside the buffer whenever nbytes > 0.
 __device__ inline rsrc_t make_rsrc(const void *p, int64_t nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
 }
@@ -155,11 +157,13 @@ __device__ inline void tile_update(rsrc_t A, rsrc_t P, rsrc_t Q, int K, int voff
             t3[cb][r] = ld1(A, voff + 8, so);
         }
     }
-    // The prefetch runs up to 4 x (STAGES - 1) columns past K without a
-    // guard: those loads fall in tile (i, j) of P's tile-row and tile (j, j)
-    // of Q's, inside the slot, and are never used. A conditional load would
-    // make the compiler's wait counts conservative at the merge and drain
-    // the whole prefetch once per loop iteration.
+    // The last STAGES - 1 prefetch slots of the loop have no step left to
+    // load: they reload step K - 4 (a clamp on the scalar offset) and are
+    // never used. The loads stay unconditional, since a guarded load would
+    // make the compiler's wait counts conservative at the merge and drain the
+    // whole prefetch once per loop iteration; and they stay inside the panel,
+    // since past it lies tile (i, j), which this unit stores afterwards (no
+    // line of it may be cached on the CU before that store).
     // The prologue keeps its program order (sched_barrier): with step 0's
     // loads issued first, the loop's first wait is the same partial count
     // as in every later iteration instead of a full drain.
@@ -180,7 +184,7 @@ __device__ inline void tile_update(rsrc_t A, rsrc_t P, rsrc_t Q, int K, int voff
         if ((k0 & (TS - 1)) == 0) __syncthreads();
 #pragma unroll
         for (int u = 0; u < STAGES; ++u) {
-            const int kl = k0 + 4 * (u + STAGES - 1);
+            const int kl = min(k0 + 4 * (u + STAGES - 1), K - 4);
             load_step(buf[(u + STAGES - 1) % STAGES], P, Q, voff, kl * COL_BYTES);
             mma_step(buf[u], t1, t2, t3);
         }
@@ -191,6 +195,22 @@ __device__ inline void tile_update(rsrc_t A, rsrc_t P, rsrc_t Q, int K, int voff
         xr[cb] = -(a + b);
         xi[cb] = a - b - t3[cb];
     }
+}
+
+// Column boundary. Tiles of L and entries of w written in one column are read
+// in later columns by other waves of the workgroup. The workgroup-scope
+// release and acquire of __syncthreads make that safe only through the CU's
+// vector L1, which all waves of the workgroup share: the compiler emits no
+// wait for stores and no L1 invalidation for them. Both are made explicit
+// here: every wave waits until its own stores have completed (vmcnt(0)), and
+// after the barrier an agent-scope acquire drops the CU's L1 (buffer_inv), so
+// every later load of L or w misses it and is served from L2, where the
+// completed stores are. A line cached before a store to it, whether by this
+// task or by the previous task in the same slot, can then never be read.
+__device__ inline void column_barrier() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt left at their maximum
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // The barriers of tile_update over K columns, for a group without a tile in
@@ -271,7 +291,7 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
         int failed = 0;
 
         for (int j = 0; valid && j < N && !failed; ++j) {
-            __syncthreads();  // previous column's readers of Dt and writers of w are done
+            column_barrier();  // previous column's readers of Dt and writers of L and w are done
             const int K = j * TS;
             const rsrc_t Qr = make_rsrc(L + tile_index(j, 0) * TS2, (int64_t)K * COL_BYTES);
             const int units = N - j;  // unit 0: diagonal tile; unit u > 0: tile (j + u, j)
@@ -424,10 +444,7 @@ __global__ __launch_bounds__(GROUP_THREADS * G, 2 / G) void likelihood_kernel(Li
                     // ---- L_ij = X Linv^H; w_i -= L_ij y_j -----------------------
                     // Y[i][c'] = sum_c X[i][c] conj(Linv[c'][c]); Linv is lower
                     // triangular, so output block cb2 needs column blocks cb <= cb2.
-                    // The tile is stored with plain global stores: written through
-                    // raw buffer stores, tiles read by the other group in later
-                    // columns came back stale now and then (no fault), which plain
-                    // stores have never shown.
+                    // The tile is read in later columns only, after column_barrier.
                     double2 *Lij = L + tile_index(i, j) * TS2 + l16 * TS + 16 * w + q;  // Y[16w + q][l16]
                     const int lt = q * TS + l16;  // Linv[l16][q] in LDS
                     double wr[4] = {0, 0, 0, 0}, wi[4] = {0, 0, 0, 0};

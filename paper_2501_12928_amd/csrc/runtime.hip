@@ -43,6 +43,7 @@ struct eor_group {
     int cap_tiles = 0;
     int64_t replays = 0;
     int64_t captures = 0;
+    eor::StreamOrder order;              // the last call's work on its stream
 };
 
 namespace {
@@ -77,6 +78,9 @@ void free_work(eor_group &g) {
 
 eor_status ensure_work(eor_group &g, int64_t want) {
     if (g.slots >= want && g.slot_tiles == eor::n_tiles(g.N_max)) return EOR_OK;
+    // queued work may still use the current slots
+    const hipError_t ed = g.order.drain();
+    if (ed != hipSuccess) return eor::hip_status(ed, "hipEventSynchronize");
     free_work(g);
     const int64_t slot_tiles = eor::n_tiles(g.N_max);
     const int64_t n_pad = g.N_max * eor::TS;
@@ -119,6 +123,9 @@ eor_status build_tasks(eor_group &g, const int64_t *B) {
     std::vector<int2> tasks;
     for (int i : order)
         for (int64_t b = 0; b < want[i]; ++b) tasks.push_back(make_int2(i, (int)b));
+    // queued work may still read the current task list
+    const hipError_t ed = g.order.drain();
+    if (ed != hipSuccess) return eor::hip_status(ed, "hipEventSynchronize");
     if (g.d_task) (void)hipFree(g.d_task);
     g.d_task = nullptr;
     g.ntask = (int64_t)tasks.size();
@@ -214,6 +221,14 @@ eor::LikeParams make_params(const eor_group &g, const double *const *theta, doub
     return p;
 }
 
+// Marks the end of a group call on s, for the group and for each instance
+// (whose A the launch reads until then).
+eor_status record_call(eor_group &g, hipStream_t s) {
+    hipError_t e = g.order.leave(s);
+    for (size_t i = 0; i < g.inst.size() && e == hipSuccess; ++i) e = g.inst[i]->c.order.leave(s);
+    return e == hipSuccess ? EOR_OK : eor::hip_status(e, "hipEventRecord");
+}
+
 // One launch of the whole group (eager or from the captured graph).
 eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta, double *const *logL,
                      int32_t *const *info, const eor::Tuning &t, bool allow_graph, hipStream_t s) {
@@ -226,10 +241,14 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
         free_work(g);
         g.N_max = N_max;
     }
+    // The launch waits for the group's previous call and for each instance's
+    // last call (a precompute that rewrote A) if they went to other streams.
+    hipError_t e = g.order.enter(s);
+    for (size_t i = 0; i < g.inst.size() && e == hipSuccess; ++i) e = g.inst[i]->c.order.enter(s);
+    if (e != hipSuccess) return eor::hip_status(e, "hipStreamWaitEvent");
     // refresh the instance descriptors (a context may have been re-precomputed)
     for (size_t i = 0; i < g.inst.size(); ++i) g.h_inst[i] = eor::inst_desc(g.inst[i]->c);
-    hipError_t e = hipMemcpyAsync(g.d_inst, g.h_inst, g.inst.size() * sizeof(eor::InstDesc),
-                                  hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(g.d_inst, g.h_inst, g.inst.size() * sizeof(eor::InstDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return eor::hip_status(e, "instance descriptors");
     const int64_t resident = eor::resident_per_cu(t) * g.num_cu;
     const int64_t want = std::min<int64_t>(g.ntask, resident);
@@ -239,7 +258,8 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
     const eor::LikeParams p = make_params(g, theta, logL, info);
     if (!(allow_graph && g.use_graph)) {
         e = eor::launch_likelihood(p, t, grid, s);
-        return e == hipSuccess ? EOR_OK : eor::hip_status(e, "group launch");
+        if (e != hipSuccess) return eor::hip_status(e, "group launch");
+        return record_call(g, s);
     }
     const bool same = g.exec && g.cap_grid == grid && g.cap_stages == t.stages && g.cap_tiles == t.tiles &&
                       std::memcmp(&g.cap_params, &p, sizeof(p)) == 0;
@@ -268,7 +288,7 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
     e = hipGraphLaunch(g.exec, s);
     if (e != hipSuccess) return eor::hip_status(e, "hipGraphLaunch");
     ++g.replays;
-    return EOR_OK;
+    return record_call(g, s);
 }
 
 eor_status check_call(const eor_group *g, const int64_t *B, const double *const *theta, double *const *logL) {
@@ -319,6 +339,7 @@ void eor_group_destroy(eor_group *g) {
     DeviceGuard dg(g->device);
     (void)hipDeviceSynchronize();
     free_work(*g);
+    g->order.destroy();
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     if (g->d_inst) (void)hipFree(g->d_inst);
     if (g->h_inst) (void)hipHostFree(g->h_inst);
@@ -333,8 +354,10 @@ eor_status eor_group_loglike(eor_group *g, const int64_t *B, const double *const
     if (st != EOR_OK) return st;
     DeviceGuard dg(g->device);
     // The instance descriptors are staged in pinned memory: wait until the
-    // previous launch of this group has copied them.
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    // previous launch of this group (on this stream or another) has copied
+    // them.
+    hipError_t e = g->order.drain();
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return eor::hip_status(e, "hipStreamSynchronize");
     return run_group(*g, B, theta, logL, info, g->tune, true, (hipStream_t)stream);
 }
@@ -393,7 +416,8 @@ eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *the
         }
     }
     // scratch outputs for the timing runs
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = g->order.drain();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return eor::hip_status(e, "hipStreamSynchronize");
     for (size_t i = 0; i < g->inst.size(); ++i) {
         double *o = nullptr;

@@ -670,6 +670,7 @@ struct eor_surrogate {
     hipStream_t cap_stream = nullptr;
     int epochs_run = 0;
     std::vector<double> best_val;
+    eor::StreamOrder order;  // the last call's work on its stream
 };
 
 namespace {
@@ -701,9 +702,12 @@ void drop_epoch_graph(eor_surrogate &s) {
 
 int64_t pad16(int64_t n) { return (n + ST - 1) / ST * ST; }
 
-// (Re)allocating any buffer a captured epoch refers to drops that graph.
+// (Re)allocating any buffer a captured epoch refers to drops that graph; work
+// queued by the previous call (on any stream) may still use the old buffer.
 hipError_t ensure_bwd(eor_surrogate &s, int64_t nb) {
     if (s.cap >= nb) return hipSuccess;
+    const hipError_t ed = s.order.drain();
+    if (ed != hipSuccess) return ed;
     drop_epoch_graph(s);
     dfree(s.H1T); dfree(s.dZ2T); dfree(s.part);
     s.cap = 0;
@@ -718,6 +722,8 @@ hipError_t ensure_bwd(eor_surrogate &s, int64_t nb) {
 
 hipError_t ensure_f(eor_surrogate &s, int64_t n) {
     if (s.f_cap >= n) return hipSuccess;
+    const hipError_t ed = s.order.drain();
+    if (ed != hipSuccess) return ed;
     drop_epoch_graph(s);
     dfree(s.f);
     s.f_cap = 0;
@@ -932,6 +938,7 @@ void eor_surrogate_destroy(eor_surrogate *s) {
     dfree(s->H1T); dfree(s->dZ2T); dfree(s->part); dfree(s->f);
     dfree(s->X); dfree(s->Y); dfree(s->idx); dfree(s->d_step);
     drop_epoch_graph(*s);
+    s->order.destroy();
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }
@@ -950,14 +957,15 @@ eor_status eor_surrogate_params(eor_surrogate *s, float *get, const float *set, 
     DevGuard dg(s->device);
     const size_t pb = (size_t)s->M * s->PP * sizeof(float);
     hipStream_t hs = (hipStream_t)stream;
-    hipError_t e = hipSuccess;
-    if (set) {
+    hipError_t e = s->order.enter(hs);
+    if (set && e == hipSuccess) {
         e = copy_params(s->params, s->PP, set, s->P, *s, hipMemcpyDeviceToDevice, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->mom, 0, pb, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->vel, 0, pb, hs);
         if (e == hipSuccess) e = hipMemsetAsync(s->d_step, 0, sizeof(int64_t), hs);
     }
     if (e == hipSuccess && get) e = copy_params(get, s->P, s->params, s->PP, *s, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = s->order.leave(hs);
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_params");
 }
 
@@ -985,6 +993,7 @@ eor_status eor_surrogate_loss_grad(eor_surrogate *s, int64_t nb, const float *x,
     DevGuard dg(s->device);
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = ensure_bwd(*s, nb);
+    if (e == hipSuccess) e = s->order.enter(hs);
     if (e != hipSuccess) return eor::hip_status(e, "surrogate activations");
     MlpArgs in = net_args(*s);
     in.X = x;
@@ -995,6 +1004,7 @@ eor_status eor_surrogate_loss_grad(eor_surrogate *s, int64_t nb, const float *x,
     if (loss) e = hipMemcpyAsync(loss, s->loss, s->M * sizeof(float), hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess && grad) e = copy_params(grad, s->P, s->grad, s->PP, *s, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = s->order.leave(hs);
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_loss_grad");
 }
 
@@ -1005,10 +1015,13 @@ eor_status eor_surrogate_adam_step(eor_surrogate *s, const eor_train_cfg *cfg, v
     DevGuard dg(s->device);
     hipStream_t hs = (hipStream_t)stream;
     const int64_t n = (int64_t)s->M * s->PP;
+    hipError_t e = s->order.enter(hs);
+    if (e != hipSuccess) return eor::hip_status(e, "hipStreamWaitEvent");
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, hs, s->params, s->grad, s->mom,
                        s->vel, n, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, s->d_step);
     hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(1), 0, hs, s->d_step, (int64_t)1);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
+    if (e == hipSuccess) e = s->order.leave(hs);
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_adam_step");
 }
 
@@ -1023,9 +1036,12 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
         return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_train: bad configuration");
     DevGuard dg(s->device);
     hipStream_t hs = (hipStream_t)stream;
+    // queued work on another stream may still use the buffers rewritten here
+    hipError_t e = s->order.drain();
+    if (e != hipSuccess) return eor::hip_status(e, "hipEventSynchronize");
     // targets: standardise by the training values' mean and standard deviation
     std::vector<double> hy(N);
-    hipError_t e = hipMemcpyAsync(hy.data(), logL, N * sizeof(double), hipMemcpyDeviceToHost, hs);
+    e = hipMemcpyAsync(hy.data(), logL, N * sizeof(double), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return eor::hip_status(e, "copy logL");
     for (double v : hy)
@@ -1163,6 +1179,7 @@ eor_status eor_surrogate_train(eor_surrogate *s, int64_t N, const double *theta,
     }
     e = hipStreamSynchronize(hs);
     if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = s->order.leave(hs);
     if (e != hipSuccess) return eor::hip_status(e, "eor_surrogate_train");
     s->epochs_run = ep;
     for (int z = 0; z < s->M; ++z) s->best_val[z] = n_val > 0 ? best[z] : NAN;
@@ -1196,6 +1213,7 @@ eor_status eor_surrogate_gate(eor_surrogate *s, int64_t B, const double *theta, 
     hipStream_t hs = (hipStream_t)stream;
     const int64_t chunk = (int64_t)1 << 20;
     hipError_t e = ensure_f(*s, std::min<int64_t>(B, chunk));
+    if (e == hipSuccess) e = s->order.enter(hs);
     if (e != hipSuccess) return eor::hip_status(e, "surrogate outputs");
     for (int64_t c0 = 0; c0 < B; c0 += chunk) {
         const int nb = (int)std::min<int64_t>(chunk, B - c0);
@@ -1219,6 +1237,7 @@ eor_status eor_surrogate_gate(eor_surrogate *s, int64_t B, const double *theta, 
                            decision ? 1 : 0, L_min, tau, decision ? decision + c0 : nullptr);
     }
     e = hipGetLastError();
+    if (e == hipSuccess) e = s->order.leave(hs);
     return e == hipSuccess ? EOR_OK : eor::hip_status(e, "surrogate inference");
 }
 

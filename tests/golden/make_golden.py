@@ -7,6 +7,10 @@ only. Run from the repository root:
     python tests/golden/make_golden.py c1 [n_sample]
     python tests/golden/make_golden.py c3 [n_sample]
     python tests/golden/make_golden.py c2
+
+For the 20000 x 4096 workload the fixture also holds theta chosen outside the
+batch (`extra_theta`): the corners and edges of the prior box [-1, 3]^12,
+points beyond it, the theta the data were drawn at, and seeded uniform draws.
 """
 import json
 import os
@@ -28,8 +32,27 @@ def digests():
         f.write(synth.gen(0).digest() + "  synth.gen(0)\n")
 
 
-def sampled(config_id, n_sample):
-    """Oracle logL at an evenly spaced sample of the config's theta batch."""
+def extra_theta(n_k, lo, hi, theta_true, n_random=11, seed=3003):
+    """Theta beyond the batch's uniform draws: the box corners, alternating
+    corners, ramps, one bin at the other end of the box, points outside the
+    box, the data's theta and seeded uniform draws."""
+    mid = 0.5 * (lo + hi)
+    alt = np.where(np.arange(n_k) % 2 == 0, lo, hi)
+    rows = [np.full(n_k, lo), np.full(n_k, hi), alt, lo + hi - alt, np.asarray(theta_true, float),
+            np.full(n_k, mid), np.linspace(lo, hi, n_k), np.linspace(hi, lo, n_k),
+            np.full(n_k, lo - 3.0), np.full(n_k, hi + 4.0)]
+    for b, base, val in ((0, lo, hi), (n_k - 1, lo, hi), (n_k // 2, hi, lo)):
+        r = np.full(n_k, base)
+        r[b] = val
+        rows.append(r)
+    rng = np.random.default_rng(seed)
+    rows.extend(rng.uniform(lo, hi, size=(n_random, n_k)))
+    return np.ascontiguousarray(np.array(rows, dtype=np.float64))
+
+
+def sampled(config_id, n_sample, with_extra=False):
+    """Oracle logL at an evenly spaced sample of the config's theta batch
+    (and, with_extra, at extra_theta)."""
     import oracle
     orc = oracle.get()
     inst = synth.gen(config_id)
@@ -38,6 +61,7 @@ def sampled(config_id, n_sample):
     t0 = time.time()
     A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
     t1 = time.time()
+    print(f"precompute {t1 - t0:.1f} s", flush=True)
     logL, info, terms = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var,
                                     inst.bin_scale, inst.theta[idx], terms=True)
     t2 = time.time()
@@ -56,6 +80,15 @@ def sampled(config_id, n_sample):
         "terms": terms.tolist(),
         "oracle_seconds": {"precompute": t1 - t0, "loglike": t2 - t1},
     }
+    if with_extra:
+        th = extra_theta(inst.n_k, inst.lo, inst.hi, inst.theta_true)
+        xl, xi, xt = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var,
+                                 inst.bin_scale, th, terms=True)
+        out["extra_theta"] = th.tolist()
+        out["extra_logL"] = xl.tolist()
+        out["extra_info"] = xi.tolist()
+        out["extra_terms"] = xt.tolist()
+        out["oracle_seconds"]["extra"] = time.time() - t2
     with open(os.path.join(HERE, f"c{config_id}_oracle_sample.json"), "w") as f:
         json.dump(out, f, indent=1)
 
@@ -87,4 +120,5 @@ if __name__ == "__main__":
     elif what == "c2":
         group_sampled()
     else:
-        sampled(int(what[1:]), int(sys.argv[2]) if len(sys.argv) > 2 else 8)
+        cid = int(what[1:])
+        sampled(cid, int(sys.argv[2]) if len(sys.argv) > 2 else 8, with_extra=(cid == 3))

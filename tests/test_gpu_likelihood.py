@@ -232,10 +232,164 @@ def test_plain_batched_workload_sampled(tuning):
 
 
 @pytest.mark.slow
-def test_metric_workload_sampled():
-    """20000 x 4096, 12 bins, B = 512 in one call (the benchmark's launch);
-    8 theta checked against stored oracle values."""
-    _sampled(3)
+def test_metric_workload():
+    """20000 x 4096, 12 bins, B = 512 in one call (the benchmark's launch).
+    Every one of the 512 logL is the same bits under the default launch
+    (two tiles per pass in eight-wave workgroups, where each group reads
+    tiles of L the other group wrote), under two four-wave workgroups per CU
+    and as a one-instance group launch. Against stored oracle values: 16 theta
+    of the batch and 24 theta outside it (the corners and edges of the prior
+    box, points beyond it, the data's theta and seeded draws), element by
+    element."""
+    import torch
+    import paper_2501_12928_amd as eor
+    path = os.path.join(GOLDEN, "c3_oracle_sample.json")
+    g = json.load(open(path))
+    inst = synth.gen(3)
+    assert inst.digest() == g["digest"], "synthetic inputs differ from the ones the oracle saw"
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
+    th = torch.from_numpy(inst.theta).cuda()
+    runs = {}
+    for t in [(4, 1, 2), (4, 2, 1)]:
+        _say(f"gpu: metric workload 20000 x 4096 B=512, tuning {t}")
+        ctx.set_tuning(*t)
+        L, info = ctx.loglike_batch(th)
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        runs[t] = L.cpu().numpy()
+    _say("gpu: metric workload as a one-instance group")
+    grp = eor.Group([ctx])
+    outs, infos = grp.loglike([th])
+    torch.cuda.synchronize()
+    assert np.all(infos[0].cpu().numpy() == 0)
+    runs["group"] = outs[0].cpu().numpy()
+    grp.close()
+    base = runs[(4, 1, 2)]
+    assert np.all(np.isfinite(base))
+    for k, v in runs.items():
+        assert np.array_equal(v, base), (k, np.max(np.abs(v - base)))
+    idx = np.array(g["index"])
+    assert len(idx) >= 16
+    _check(base[idx], np.array(g["logL"]))
+    xt = np.array(g["extra_theta"])
+    assert xt.shape == (24, inst.n_k)
+    _say("gpu: metric workload, 24 theta outside the batch")
+    ctx.set_tuning(4, 1, 2)
+    L, info = ctx.loglike_batch(torch.from_numpy(xt).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(info.cpu().numpy(), np.array(g["extra_info"]))
+    _check(L.cpu().numpy(), np.array(g["extra_logL"]))
+    ctx.close()
+
+
+def test_precompute_rejects_bad_leading_dimension():
+    """ldT < n, and the other argument errors of eor_precompute, come back as
+    EOR_ERR_ARG before any device work; the context stays usable."""
+    import torch
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=5, m=90, n=70, n_k=2, n_theta=3)
+    T = torch.from_numpy(inst.T).cuda()
+    nv = torch.from_numpy(inst.noise_var).cuda()
+    d = torch.from_numpy(inst.d).cuda()
+    bins = np.ascontiguousarray(inst.bin_of, dtype=np.int32)
+    fv = np.ascontiguousarray(inst.fixed_var)
+    ctx = eor.Context(0)
+    L = eor.lib()
+    args = lambda m, n, ld, nk=inst.n_k: (ctx.handle, m, n, T.data_ptr(), ld, nv.data_ptr(), d.data_ptr(), nk,
+                                          bins.ctypes.data, fv.ctypes.data, None, 0, None)
+    _say("gpu: precompute argument errors")
+    assert L.eor_precompute(*args(90, 70, 69)) == eor.EOR_ERR_ARG
+    assert b"ldT" in L.eor_last_error()
+    assert L.eor_precompute(*args(90, 70, 0)) == eor.EOR_ERR_ARG
+    assert L.eor_precompute(*args(0, 70, 70)) == eor.EOR_ERR_ARG
+    assert L.eor_precompute(*args(90, 70, 70, nk=1)) == eor.EOR_ERR_ARG   # bin 1 out of range
+    assert L.eor_loglike_batch(ctx.handle, 3, None, None, None, None) == eor.EOR_ERR_STATE
+    assert L.eor_precompute(*args(90, 70, 70)) == eor.EOR_OK
+    got, info = ctx.loglike_batch(torch.from_numpy(inst.theta).cuda())
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    ctx.close()
+
+
+def test_workspace_limit(orc):
+    """A workspace budget caps the theta in flight without changing a bit;
+    a budget below one theta's slot returns EOR_ERR_OOM before any launch
+    (the outputs stay as they were)."""
+    import torch
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=17, m=500, n=300, n_k=4, n_theta=40)
+    ref, _ = orc.loglike_instance(inst)
+    n_pad = 320
+    # one slot: N (N + 1) / 2 packed tiles of 64 x 64 complex128, plus the solve vector
+    N = n_pad // 64
+    slot = N * (N + 1) // 2 * 64 * 64 * 16 + 16 * n_pad
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
+    th = torch.from_numpy(inst.theta).cuda()
+    _say("gpu: workspace limit, no limit")
+    a, _ = ctx.loglike_batch(th)
+    torch.cuda.synchronize()
+    a = a.cpu().numpy()
+    for k in (3, 1):
+        _say(f"gpu: workspace limit of {k} slots")
+        ctx.set_workspace_limit(k * slot)
+        b, info = ctx.loglike_batch(th)
+        torch.cuda.synchronize()
+        assert np.all(info.cpu().numpy() == 0)
+        assert np.array_equal(b.cpu().numpy(), a)
+    assert np.all(np.abs(a - ref) <= tol(ref))
+    ctx.set_workspace_limit(slot - 1)
+    out = torch.full((40,), 7.0, dtype=torch.float64, device="cuda")
+    inf = torch.full((40,), 9, dtype=torch.int32, device="cuda")
+    L = eor.lib()
+    st = L.eor_loglike_batch(ctx.handle, 40, th.data_ptr(), out.data_ptr(), inf.data_ptr(), None)
+    assert st == eor.EOR_ERR_OOM, st
+    assert b"workspace" in L.eor_last_error()
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0) and torch.all(inf == 9)
+    ctx.set_workspace_limit(0)
+    c, _ = ctx.loglike_batch(th)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), a)
+    ctx.close()
+
+
+def test_calls_on_two_streams(orc):
+    """Back-to-back calls on one context from two streams share the task
+    counter and the workspace: the second waits for the first, and both
+    give the bits of calls made one after the other on one stream. The same
+    for a group call on a third stream right after a context call."""
+    import torch
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=23, m=700, n=520, n_k=5, n_theta=300)
+    ctx = eor.Context(0)
+    ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
+                   torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
+    th1 = torch.from_numpy(inst.theta[:300]).cuda()
+    th2 = torch.from_numpy(inst.theta[::-1].copy()).cuda()
+    _say("gpu: one stream")
+    r1, _ = ctx.loglike_batch(th1)
+    r2, _ = ctx.loglike_batch(th2)
+    torch.cuda.synchronize()
+    r1, r2 = r1.cpu().numpy(), r2.cpu().numpy()
+    assert np.array_equal(r2, r1[::-1])
+    s1, s2, s3 = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    grp = eor.Group([ctx])
+    for rep in range(3):
+        _say(f"gpu: two streams, repeat {rep}")
+        torch.cuda.synchronize()
+        a, _ = ctx.loglike_batch(th1, stream=s1)
+        b, _ = ctx.loglike_batch(th2, stream=s2)
+        outs, _ = grp.loglike([th1], stream=s3)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), r1)
+        assert np.array_equal(b.cpu().numpy(), r2)
+        assert np.array_equal(outs[0].cpu().numpy(), r1)
+    grp.close()
+    ctx.close()
 
 
 def test_largest_shape_block_rotation():

@@ -3,7 +3,13 @@ a small dataset: the gated run agrees with the plain run (same seed) in
 evidence and posterior, every accepted point carries its exact logL, and
 the surrogate rejects proposals without exact calls with a false-rejection
 rate within 5% of the audited ones. (What the gate saves in time depends
-on the cost of an exact call; the benchmark measures it at n = 4096.)"""
+on the cost of an exact call; the benchmark measures it at n = 4096.)
+
+Agreement is the reading's: per-bin posterior means within 0.1 posterior
+standard deviation and |d ln Z| within 3 sqrt(H / n_live). Once the gate is
+trained the two runs draw different proposals, so they differ like two
+independent runs; 1000 live points keep that difference well inside the
+bar."""
 import numpy as np
 import pytest
 
@@ -24,13 +30,13 @@ def test_gated_sampler_agrees_with_plain(orc):
     sur = eor.Surrogate(inst.n_k, inst.lo, inst.hi, n_members=5, hidden=64, seed=1)
     cfg = eor.train_cfg(epochs=40, minibatch=256, patience=8, lr=1e-3, seed=5)
     print("gpu: plain and gated nested sampling, n=192, 3 bins", flush=True)
-    plain, gated, cmp = run_plain_and_gated(ctx, inst.n_k, inst.lo, inst.hi, sur, n_live=200, seed=3,
+    plain, gated, cmp = run_plain_and_gated(ctx, inst.n_k, inst.lo, inst.hi, sur, n_live=1000, seed=3,
                                             tau=0.05, first_train=1500, retrain_every=250, window=3000,
                                             margin=30.0, train_cfg=cfg, batch=256, dlogz=0.05,
                                             audit_frac=0.05)
     print(cmp, flush=True)
     assert abs(cmp["logz_plain"] - cmp["logz_gated"]) < cmp["logz_tolerance"]
-    assert cmp["max_dmean_over_sigma"] < 0.25
+    assert cmp["max_dmean_over_sigma"] < 0.1
     assert cmp["gate_rejected"] > 0
     # what the trained network gains: exact calls the plain run makes and the gated one does not
     assert cmp["exact_calls_gated"] < cmp["exact_calls_plain"]

@@ -102,3 +102,52 @@ def test_ensemble_spread_and_gate():
     np.testing.assert_allclose(s, np.sqrt(((preds - preds.mean(0)) ** 2).mean(0)), rtol=1e-12)
     dec = mlp.gate(np.array([1.0, 1.0, 5.0, 5.0]), np.array([0.01, 0.2, 0.01, 0.2]), 3.0, 0.05)
     np.testing.assert_array_equal(dec, [0, 1, 1, 1])
+
+
+def test_scale_inputs_fixed_points():
+    """The prior box maps onto [-1, 1] input by input (reading of the
+    surrogate's inputs): each lower edge goes to -1, each upper edge to +1,
+    the midpoint to 0 and the three-quarter point to 0.5, with a box of its
+    own per input. These four points fix an affine map per input."""
+    lo = np.array([-1.0, 0.0, 2.0, -5.0])
+    hi = np.array([3.0, 10.0, 2.5, -4.0])
+    np.testing.assert_array_equal(mlp.scale_inputs(lo[None, :], lo, hi), [[-1.0] * 4])
+    np.testing.assert_array_equal(mlp.scale_inputs(hi[None, :], lo, hi), [[1.0] * 4])
+    np.testing.assert_allclose(mlp.scale_inputs(((lo + hi) / 2)[None, :], lo, hi), [[0.0] * 4], atol=1e-15)
+    np.testing.assert_allclose(mlp.scale_inputs((lo + 0.75 * (hi - lo))[None, :], lo, hi), [[0.5] * 4],
+                               atol=1e-15)
+    # a row mixing edges of different inputs
+    th = np.array([[3.0, 0.0, 2.25, -5.0]])
+    np.testing.assert_allclose(mlp.scale_inputs(th, lo, hi), [[1.0, -1.0, 0.0, -1.0]], atol=1e-15)
+
+
+def _constant_member(n_in, H, value):
+    """A member whose output is `value` for every input: every weight zero
+    and the output bias set."""
+    p = np.zeros(mlp.n_params(n_in, H))
+    p[-1] = value
+    return p
+
+
+def test_ensemble_destandardisation_constant_members():
+    """Targets are standardised for training, so a member's output f stands
+    for y_mean + y_std f in logL units (reading of the surrogate's targets),
+    and the spread is the population standard deviation (ddof = 0) of the
+    members in those units. Members with constant outputs fix both."""
+    n_in, H = 3, 5
+    th = np.array([[-1.0, 0.0, 3.0], [2.0, 2.0, 2.0], [0.5, -0.5, 1.5]])
+    y_mean, y_std = -58000.0, 250.0
+    # identical members: mean = y_mean + y_std f, spread exactly 0
+    params = [_constant_member(n_in, H, 0.4)] * 5
+    mu, s = mlp.ensemble(params, th, -1.0, 3.0, y_mean, y_std, n_in, H)
+    np.testing.assert_allclose(mu, y_mean + y_std * 0.4, rtol=1e-15)
+    np.testing.assert_array_equal(s, 0.0)
+    # outputs (-1, 1, -1, 1, 0) a: mean y_mean, spread y_std a sqrt(4/5)
+    a = 0.02
+    params = [_constant_member(n_in, H, v * a) for v in (-1.0, 1.0, -1.0, 1.0, 0.0)]
+    mu, s = mlp.ensemble(params, th, -1.0, 3.0, y_mean, y_std, n_in, H)
+    np.testing.assert_allclose(mu, y_mean, rtol=1e-15)
+    np.testing.assert_allclose(s, y_std * a * math.sqrt(0.8), rtol=1e-12)
+    # the gate reads the spread in logL units: 0.05 * 250 = 12.5 > tau
+    assert np.all(mlp.gate(mu - 100.0, s, y_mean, 0.05) == 1)
+    assert np.all(mlp.gate(mu - 100.0, s / (y_std * a * 100.0), y_mean, 0.05) == 0)
