@@ -342,6 +342,25 @@ eor_status eor_surrogate_gate(eor_surrogate *s, int64_t B, const double *theta, 
                               int32_t *decision, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as eor_surrogate_gate, with the same arguments, from the same
+ * kernels, but the members' outputs of the call are kept in a fixed scratch
+ * array inside the library instead of a buffer the surrogate grows, so the
+ * call allocates nothing (its first call on a device looks up that device's
+ * copy of the array; the surrogate must have been trained, or given its
+ * standardisation, before).
+ * Limit: B * n_members <= 2^22 (16 MiB of FP32 per device, held until the
+ * process ends); a larger B returns EOR_ERR_ARG before any launch.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one
+ * GPU (from any surrogate, on any stream) race and must be ordered by the
+ * caller. Errors: as eor_surrogate_gate, and EOR_ERR_ARG as above.
+ */
+eor_status eor_surrogate_gate_noalloc(eor_surrogate *s, int64_t B, const double *theta, double L_min,
+                                      double tau, double *mean, double *spread, float *members,
+                                      int32_t *decision, void *stream);
+
+/*
  * Stable compaction: the rows s of rows (device double [n x n_cols]) with
  * keep[s] != 0 are copied, in order, to rows_out (may be NULL), their
  * indices to index_out (device int32, may be NULL), and their number to

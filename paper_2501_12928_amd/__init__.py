@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.eor_surrogate_adam_step.argtypes = [_P, ctypes.POINTER(TrainCfg), _P]
         L.eor_surrogate_infer.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
         L.eor_surrogate_gate.argtypes = [_P, _I64, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P]
+        L.eor_surrogate_gate_noalloc.argtypes = [_P, _I64, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P,
+                                                 _P, _P]
         L.eor_compact_rows.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P]
         L.eor_probe_fp64_mfma.argtypes = [ctypes.c_int, _I64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
@@ -110,6 +112,7 @@ def lib() -> ctypes.CDLL:
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
                      "eor_surrogate_adam_step", "eor_surrogate_infer", "eor_surrogate_gate",
+                     "eor_surrogate_gate_noalloc",
                      "eor_compact_rows", "eor_probe_fp64_mfma", "eor_forward_model", "eor_loglike_host",
                      "eor_loglike_host_plan"):
             getattr(L, name).restype = ctypes.c_int

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <random>
@@ -35,6 +36,9 @@
 #include <vector>
 
 #include "common.h"
+
+// Fixed device scratch of eor_surrogate_gate_noalloc (see kGateScratchFloats).
+static __device__ __align__(256) float scratch[(int64_t)1 << 22];
 
 namespace {
 
@@ -859,6 +863,17 @@ hipError_t copy_params(float *dst, int64_t dst_stride, const float *src, int64_t
                             (size_t)s.P * sizeof(float), (size_t)s.M, kind, st);
 }
 
+// Scratch of eor_surrogate_gate_noalloc: the members' outputs of one call,
+// B * n_members floats at most. Every GPU the library runs on holds its own
+// copy until the process ends. In host code `scratch` names a host-side
+// stand-in, not the device array: host code uses the per-device address
+// that hipGetSymbolAddress returns (scratch_address), never the name.
+constexpr int64_t kGateScratchFloats = (int64_t)1 << 22;  // 16 MiB
+static_assert(sizeof(scratch) == kGateScratchFloats * sizeof(float), "scratch size");
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+
 eor_status need(const eor_surrogate *s) {
     if (!s) return eor::fail_status(EOR_ERR_ARG, "surrogate is NULL");
     return EOR_OK;
@@ -1194,6 +1209,57 @@ eor_status eor_surrogate_report(const eor_surrogate *s, int32_t *epochs_run, dou
     if (val_loss)
         for (int z = 0; z < s->M; ++z) val_loss[z] = s->best_val[z];
     return EOR_OK;
+}
+
+eor_status eor_surrogate_gate_noalloc(eor_surrogate *s, int64_t B, const double *theta, double L_min, double tau,
+                                      double *mean, double *spread, float *members, int32_t *decision,
+                                      void *stream) {
+    eor_status st = need(s);
+    if (st != EOR_OK) return st;
+    if (!s->trained) return eor::fail_status(EOR_ERR_STATE, "surrogate: train it (or set its standardisation) first");
+    if (B < 0 || (B > 0 && !theta)) return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_gate_noalloc: bad batch");
+    if (B > kGateScratchFloats / s->M)
+        return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_gate_noalloc: B x n_members exceeds the fixed scratch of "
+                                             "2^22 floats (B <= " + std::to_string(kGateScratchFloats / s->M) + ")");
+    if (B == 0) return EOR_OK;
+    if (s->device < 0 || s->device >= kMaxDevices)
+        return eor::fail_status(EOR_ERR_ARG, "eor_surrogate_gate_noalloc: device index beyond 63");
+    DevGuard dg(s->device);
+    float *f = nullptr;
+    {
+        // Set-up, once per device with that device current: the device
+        // address of this GPU's copy of the scratch array.
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_dev[s->device]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return eor::hip_status(e, "hipGetSymbolAddress(scratch)");
+            g_scratch_dev[s->device] = (float *)p;
+        }
+        f = g_scratch_dev[s->device];
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = s->order.enter(hs);
+    if (e != hipSuccess) return eor::hip_status(e, "hipStreamWaitEvent");
+    MlpArgs in = net_args(*s);
+    in.theta = theta;
+    in.lo = s->d_lo;
+    in.hi = s->d_hi;
+    in.nb = (int)B;
+    in.f = f;  // written for every (member, sample) of this call before it is read
+    in.fz = B;
+    launch_forward(in, s->NT, s->M, hs);
+    if (members) {
+        e = hipMemcpyAsync(members, f, (size_t)s->M * B * sizeof(float), hipMemcpyDeviceToDevice, hs);
+        if (e != hipSuccess) return eor::hip_status(e, "member outputs");
+    }
+    hipLaunchKernelGGL(ensemble_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, hs, f, s->M, B, s->ymean,
+                       s->ystd, mean, spread, decision ? 1 : 0, L_min, tau, decision);
+    e = hipGetLastError();
+    // The event that orders this handle's calls is created by an earlier
+    // call (training); this call only records it, which allocates nothing.
+    if (e == hipSuccess && s->order.ev) e = s->order.leave(hs);
+    return e == hipSuccess ? EOR_OK : eor::hip_status(e, "eor_surrogate_gate_noalloc");
 }
 
 eor_status eor_surrogate_infer(eor_surrogate *s, int64_t B, const double *theta, double *mean, double *spread,
