@@ -225,7 +225,11 @@ def bench_group(args):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "likelihood_kernel",
                      "launch_ms": ms, "flops_per_launch": flops},
-        "tuning": {"stages": stages, "wg_per_cu": wg, "tiles_per_pass": tiles, "graph": list(g.tuning()[3:])},
+        "tuning": {"stages": stages, "wg_per_cu": wg, "tiles_per_pass": tiles, "graph": list(g.tuning()[3:]),
+                   "tile_side_per_bucket": dict(zip(("n<=512", "n<=1024", "n<=2048", "n<=4096", "n>4096"),
+                                                    g.tile_sizes())),
+                   "tile_timing_ms": {k.split("|")[1]: v for k, v in json.load(open(cache)).items()
+                                      if k.endswith("|tile")}},
         "precompute_s_total": t_pre, "all_info_zero": ok}))
     g.close()
     for c in ctxs:
@@ -268,52 +272,147 @@ def bench_stress(args):
     print(json.dumps(out))
 
 
+def gate_settings(args):
+    """Surrogate and gate settings of the gated runs, from the command line."""
+    import paper_2501_12928_amd as eor
+    cfg = eor.train_cfg(epochs=args.train_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=5)
+    # Warm retraining may run longer than the first training: late in the run
+    # the ensemble keeps improving well past 300 epochs. A short one can be
+    # worse than none: the members stay close to their common starting
+    # point, agree with each other and are wrong together, which the audits
+    # show as false rejections.
+    rcfg = None if not args.retrain_epochs else eor.train_cfg(
+        epochs=args.retrain_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=6)
+    band = None if args.band_above <= 0 else (args.band_below, args.band_above)
+    kw = dict(tau=args.tau, first_train=args.first_train, retrain_every=args.retrain_every, window=args.window,
+              margin=args.margin, train_kwargs={"cfg": cfg}, retrain_kwargs=None if rcfg is None else {"cfg": rcfg},
+              band=band, guard=args.guard, stale_gap=args.stale_gap, whiten=args.whiten, cold=args.cold, seed=11)
+    text = (f"n_live={args.n_live}, gate tau={args.tau}, first training after {args.first_train} exact "
+            f"evaluations ({args.train_epochs} epochs), retrain every {args.retrain_every} iterations on the last "
+            f"{args.window} ({args.retrain_epochs or args.train_epochs} epochs, warm), "
+            + (f"targets censored to [L_min - {args.band_below}, L_min + {args.band_above}] (band re-centred after "
+               f"the threshold climbs {args.band_above / 2}, at most every {args.stale_gap} iterations; guard "
+               f"{args.guard})" if band else f"within {args.margin} of the threshold")
+            + (", inputs mapped to the training box" if args.whiten else "")
+            + (", every training from fresh weights" if args.cold else "")
+            + ", exact calls of 512 proposals the gate is unsure of")
+    return kw, text
+
+
+def gated_pair(ctx, n_k, lo, hi, args, seed=7, progress=2000):
+    """The plain and the gated nested-sampling run on one context (same seed),
+    and their comparison."""
+    import paper_2501_12928_amd as eor
+    from paper_2501_12928_amd.sampler import GatedLikelihood, NestedSampler, compare_runs, exact_gpu
+    kw, text = gate_settings(args)
+    loglike = exact_gpu(ctx)
+    plain = NestedSampler(loglike, n_k, lo, hi, n_live=args.n_live, dlogz=0.01, batch=512, seed=seed,
+                          progress=progress).run()
+    sur = eor.Surrogate(n_k, -1.0 if args.whiten else lo, 1.0 if args.whiten else hi, n_members=5, hidden=256, seed=1)
+    gated = NestedSampler(loglike, n_k, lo, hi, n_live=args.n_live, dlogz=0.01, batch=512, seed=seed,
+                          gate=GatedLikelihood(sur, **kw), audit_frac=0.01, pool_factor=args.pool_factor,
+                          progress=progress).run()
+    sur.close()
+    cmp = compare_runs(plain, gated, args.n_live)
+    # accepted points carry exact logL: re-evaluate a sample of them
+    idx = np.random.default_rng(0).choice(gated.samples.shape[0], 64, replace=False)
+    cmp["accepted_max_abs_dlogL"] = float(np.max(np.abs(loglike(gated.samples[idx]) - gated.logl[idx])))
+    cmp["accepted_checked"] = 64
+    return plain, gated, cmp, text
+
+
+def gated_leg(ctx, inst, args):
+    """The gated half of the headline metric on the benchmark's own dataset:
+    plain and surrogate-gated nested sampling with the same seed, both on
+    the batched FP64 likelihood (n_live reduced to keep the default run
+    short)."""
+    import copy
+    a = copy.copy(args)
+    a.n_live = args.gated_n_live
+    a.first_train = max(2000, args.first_train * args.gated_n_live // 500)
+    print(f"bench: gated leg, plain and gated nested sampling with {a.n_live} live points", file=sys.stderr,
+          flush=True)
+    plain, gated, cmp, text = gated_pair(ctx, inst.n_k, inst.lo, inst.hi, a, progress=2000)
+    keys = ("proposals_plain", "proposals_gated", "proposals_per_s_plain", "proposals_per_s_gated", "speedup",
+            "exact_calls_plain", "exact_calls_gated", "exact_calls_avoided_frac", "logz_plain", "logz_gated",
+            "logz_tolerance", "max_dmean_over_sigma", "max_dstd_rel", "gate_rejected", "audited",
+            "false_rejections", "accepted_max_abs_dlogL", "accepted_checked", "confident_checked",
+            "confident_max_err", "wall_plain_s", "wall_gated_s", "retrains", "train_s")
+    out = {k: cmp[k] for k in keys}
+    out["dlogz"] = cmp["logz_gated"] - cmp["logz_plain"]
+    out["metric"] = "proposals judged per second, plain batched vs surrogate-gated nested sampling"
+    out["config"] = text + f" (n_live {a.n_live}, first training after {a.first_train})"
+    return out
+
+
 def bench_gated(args):
     """Nested sampling on the 12-bin n = 4096 dataset, once with every
     proposal evaluated exactly and once gated by the surrogate ensemble
     (same seed): throughput in proposals judged per second, exact calls
-    avoided, wall-clock speedup, and agreement of evidence and posterior."""
+    avoided, wall-clock speedup, and agreement of evidence and posterior.
+
+    --phase both runs the two in this process. --phase plain / gated runs one
+    of them, stopping after --time-limit seconds with its state in
+    --checkpoint (continued by --resume) and writing the finished run to
+    --result-out; --phase compare compares two such results."""
     import torch
     import synth
     import paper_2501_12928_amd as eor
-    from paper_2501_12928_amd.sampler import run_plain_and_gated
+    from paper_2501_12928_amd.sampler import (GatedLikelihood, NestedSampler, compare_runs, exact_gpu,
+                                              load_result, save_result)
+    kw, text = gate_settings(args)
     inst = synth.gen(args.gated_config, n_theta=1)
+    head = {"unit": "proposals/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64 likelihood, f32 surrogate",
+            "data": "synthetic", "config": {"workload": f"T complex128 {inst.m}x{inst.n}, {inst.n_k} k-bins, "
+                                                        + text}}
+    if args.phase == "compare":
+        plain, gated = load_result(args.plain_result), load_result(args.gated_result)
+        cmp = compare_runs(plain, gated, args.n_live)
+        m, sd = gated.posterior_moments()
+        print(json.dumps({"metric": "proposals judged per second by nested sampling at n=4096 complex FP64, "
+                                    "surrogate-gated", "value": gated.n_proposed / gated.wall_s, **head,
+                          "plain_proposals_per_s": plain.n_proposed / plain.wall_s, "comparison": cmp,
+                          "gated_stats": {"retrains": gated.n_retrain, "train_s": gated.t_train_s,
+                                          "gate_s": gated.t_gate_s, "exact_s": gated.t_exact_s},
+                          "posterior_mean": m.tolist(), "posterior_std": sd.tolist(),
+                          "theta_true": inst.theta_true.tolist(),
+                          "power_recovery": gated.power_summary(inst.theta_true)}))
+        return
     ctx = eor.Context(0)
     ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
                    torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var)
-    sur = eor.Surrogate(inst.n_k, inst.lo, inst.hi, n_members=5, hidden=256, seed=1)
-    cfg = eor.train_cfg(epochs=args.train_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=5)
-    # Warm retraining runs longer than the first training by default: late in the
-    # run the ensemble keeps improving well past 300 epochs (the validation loss
-    # falls about sixtyfold by 1000), which is what brings its spread under tau.
-    # A short one is worse than none: the members stay close to their common
-    # starting point, agree with each other and are wrong together, which the
-    # audits show as false rejections.
-    rcfg = None if not args.retrain_epochs else eor.train_cfg(
-        epochs=args.retrain_epochs, minibatch=args.train_minibatch, patience=30, lr=1e-3, seed=6)
-    plain, gated, cmp = run_plain_and_gated(ctx, inst.n_k, inst.lo, inst.hi, sur, n_live=args.n_live, seed=7,
-                                            tau=args.tau, first_train=args.first_train,
-                                            retrain_every=args.retrain_every, window=args.window,
-                                            margin=args.margin, train_cfg=cfg, batch=512, dlogz=0.01,
-                                            audit_frac=0.01, pool_factor=args.pool_factor, progress=2000,
-                                            retrain_cfg=rcfg)
-    m, sd = gated.posterior_moments()
-    print(json.dumps({
-        "metric": "proposals judged per second by nested sampling at n=4096 complex FP64, surrogate-gated",
-        "value": gated.n_proposed / gated.wall_s, "unit": "proposals/s", "n_gpus": 1,
-        "higher_is_better": True, "dtype": "f64 likelihood, f32 surrogate", "data": "synthetic",
-        "config": {"workload": f"T complex128 {inst.m}x{inst.n}, {inst.n_k} k-bins, n_live={args.n_live}, "
-                               f"gate tau={args.tau}, first training after {args.first_train} exact "
-                               f"evaluations ({args.train_epochs} epochs), retrain every {args.retrain_every} "
-                               f"iterations on the last {args.window} within {args.margin} of the threshold "
-                               f"({args.retrain_epochs or args.train_epochs} epochs, warm), exact calls of "
-                               f"512 proposals the gate is unsure of"},
-        "plain_proposals_per_s": plain.n_proposed / plain.wall_s,
-        "comparison": cmp,
-        "posterior_mean": m.tolist(), "posterior_std": sd.tolist(),
-        "theta_true": inst.theta_true.tolist(),
-        "power_recovery": gated.power_summary(inst.theta_true)}))
-    sur.close()
+    if args.phase == "both":
+        plain, gated, cmp, _ = gated_pair(ctx, inst.n_k, inst.lo, inst.hi, args)
+        m, sd = gated.posterior_moments()
+        print(json.dumps({"metric": "proposals judged per second by nested sampling at n=4096 complex FP64, "
+                                    "surrogate-gated", "value": gated.n_proposed / gated.wall_s, **head,
+                          "plain_proposals_per_s": plain.n_proposed / plain.wall_s, "comparison": cmp,
+                          "posterior_mean": m.tolist(), "posterior_std": sd.tolist(),
+                          "theta_true": inst.theta_true.tolist(),
+                          "power_recovery": gated.power_summary(inst.theta_true)}))
+        ctx.close()
+        return
+    sur = None
+    gate = None
+    if args.phase == "gated":
+        sur = eor.Surrogate(inst.n_k, -1.0 if args.whiten else inst.lo, 1.0 if args.whiten else inst.hi,
+                            n_members=5, hidden=256, seed=1)
+        gate = GatedLikelihood(sur, **kw)
+    ns = NestedSampler(exact_gpu(ctx), inst.n_k, inst.lo, inst.hi, n_live=args.n_live, dlogz=0.01, batch=512,
+                       seed=7, gate=gate, audit_frac=0.01, pool_factor=args.pool_factor, progress=2000)
+    r = ns.run(time_limit=args.time_limit, checkpoint=args.checkpoint, resume=args.resume)
+    if r is None:
+        print(json.dumps({"phase": args.phase, "stopped": True, "checkpoint": args.checkpoint,
+                          "exact_calls": ns.stats["n_exact"], "proposals": ns.stats["n_proposed"]}))
+    else:
+        save_result(args.result_out, r)
+        print(json.dumps({"phase": args.phase, "stopped": False, "result": args.result_out,
+                          "iterations": r.iterations, "exact_calls": r.n_exact, "proposals": r.n_proposed,
+                          "wall_s": r.wall_s, "logz": r.logz, "gate_rejected": r.n_gate_rejected,
+                          "audited": r.n_audited, "false_rejections": r.n_false_reject,
+                          "retrains": r.n_retrain, "train_s": r.t_train_s}))
+    if sur is not None:
+        sur.close()
     ctx.close()
 
 
@@ -537,6 +636,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision report")
+    ap.add_argument("--no-gated", action="store_true", help="skip the gated nested-sampling leg")
+    ap.add_argument("--gated-n-live", type=int, default=200,
+                    help="live points of the default run's gated leg (plain and gated)")
     ap.add_argument("--workload", choices=["metric", "group", "gated", "stress", "surrogate", "instrument", "ooc"], default="metric",
                     help="metric: 20000x4096, B=512 (default); group: 48 uneven sub-band instances; "
                          "gated: nested sampling at 20000x4096 without and with the surrogate gate; "
@@ -556,6 +658,21 @@ def main():
                     help="epochs of each warm retraining (0: as the first training)")
     ap.add_argument("--train-minibatch", type=int, default=512)
     ap.add_argument("--pool-factor", type=int, default=1)
+    ap.add_argument("--band-below", type=float, default=5.0,
+                    help="gated: censor training targets this far below the threshold")
+    ap.add_argument("--band-above", type=float, default=0.0,
+                    help="gated: ... and this far above it (0: no censoring; train near the threshold)")
+    ap.add_argument("--guard", type=float, default=1.0)
+    ap.add_argument("--whiten", action="store_true", help="gated: map inputs to the training data's box")
+    ap.add_argument("--cold", action="store_true", help="gated: every training from fresh weights")
+    ap.add_argument("--stale-gap", type=int, default=250)
+    ap.add_argument("--phase", choices=["both", "plain", "gated", "compare"], default="both")
+    ap.add_argument("--time-limit", type=float, default=None, help="gated workload, one phase: stop after this many s")
+    ap.add_argument("--checkpoint", default=None)
+    ap.add_argument("--resume", default=None)
+    ap.add_argument("--result-out", default=None)
+    ap.add_argument("--plain-result", default=None)
+    ap.add_argument("--gated-result", default=None)
     ap.add_argument("--instrument-sample", action="store_true",
                     help="instrument workload: also run nested sampling and report the recovered spectrum")
     ap.add_argument("--ooc-mib", type=int, default=256, help="ooc workload: device window in MiB")
@@ -688,6 +805,8 @@ def main():
         "tuning": dict(zip(("stages", "wg_per_cu", "tiles_per_pass"), ctx.tuning())),
         "gated": None,
     }
+    if not args.no_gated:
+        out["gated"] = gated_leg(ctx, inst, args)
     if not args.no_precision:
         out["precision"] = precision_report(ctx, inst, T, nv, d, theta, logL.clone())
     if not args.no_cpu_baseline:

@@ -177,13 +177,27 @@ eor_status eor_set_workspace_limit(eor_ctx *ctx, size_t bytes);
  * summation order of the tile updates, which is the same for all):
  *   stages          k-steps of 4 columns the panel update prefetches (2 or 4)
  *   wg_per_cu       theta in flight per compute unit (1 or 2)
- *   tiles_per_pass  tiles of a column updated per pass over its panel: 1
- *                   (workgroups of 4 waves), or 2 (workgroups of 8 waves,
- *                   which then need wg_per_cu = 1)
+ *   tiles_per_pass  1: workgroups of 4 waves; 2: workgroups of 8 waves,
+ *                   which then need wg_per_cu = 1. With 64-wide tiles (see
+ *                   eor_set_tile_size) that is 1 or 2 tiles of a column
+ *                   updated per pass over its panel, with 32-wide tiles 2 or 4.
  * Default: 4, 1, 2. Errors: EOR_ERR_ARG for any other combination.
  */
 eor_status eor_set_tuning(eor_ctx *ctx, int32_t stages, int32_t wg_per_cu, int32_t tiles_per_pass);
 eor_status eor_get_tuning(const eor_ctx *ctx, int32_t *stages, int32_t *wg_per_cu, int32_t *tiles_per_pass);
+
+/*
+ * Side of the square tiles in which this context's eor_loglike_batch /
+ * eor_loglike_terms factor Sigma (the blocked Cholesky that the "Running
+ * BayesEoR" footnote puts on the GPU): 64 (default) or 32. Smaller tiles make
+ * the serial factorisation of each diagonal tile cheaper and the panel
+ * updates less efficient; small n gains, large n loses. A stays in 64-wide
+ * storage tiles either way. The results differ between the two sides only by
+ * the summation order of the tile updates (far inside the parity tolerance).
+ * Errors: EOR_ERR_ARG (NULL ctx or argument, a side other than 32 or 64).
+ */
+eor_status eor_set_tile_size(eor_ctx *ctx, int32_t ts);
+eor_status eor_get_tile_size(const eor_ctx *ctx, int32_t *ts);
 
 /*
  * Groups: many datasets of uneven size (e.g. independent frequency
@@ -223,6 +237,15 @@ eor_status eor_group_set_graph(eor_group *g, int32_t enable);
 /* Set the group's launch choices (meaning and limits as eor_set_tuning). */
 eor_status eor_group_set_tuning(eor_group *g, int32_t stages, int32_t wg_per_cu, int32_t tiles_per_pass);
 
+/*
+ * Tile side (32 or 64, as eor_set_tile_size) per size bucket of an instance's
+ * n: ts_per_bucket[5] for n <= 512, <= 1024, <= 2048, <= 4096 and larger. One
+ * launch mixes instances of either side. Default: 64 for every bucket.
+ * Errors: EOR_ERR_ARG (NULL argument, a side other than 32 or 64).
+ */
+eor_status eor_group_set_tile_sizes(eor_group *g, const int32_t *ts_per_bucket);
+eor_status eor_group_tile_sizes(const eor_group *g, int32_t *ts_per_bucket);
+
 /* Current launch choices of the group, and how many times it launched a
  * graph and captured one so far (any output may be NULL). */
 eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per_cu,
@@ -231,14 +254,17 @@ eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per
 
 /*
  * Autotuner: times the group on the given batch (same arguments as
- * eor_group_loglike, outputs discarded) for every candidate launch (panel
- * prefetch depth 2 or 4 k-steps x {1 tile per pass with 1 or 2 theta in
- * flight per CU, 2 tiles per pass with 1}) and keeps
- * the fastest. With cache_path (may be NULL), the choice is stored in a JSON
- * file keyed by "<gfx arch>|<size bucket of the largest n: n<=512, n<=1024,
- * n<=2048, n<=4096, n>4096>|<single or group>", and an existing entry is
- * used without timing unless force != 0. A lone dataset is tuned as a
- * one-instance group. Synchronises the stream.
+ * eor_group_loglike, outputs discarded) for every candidate launch shape
+ * (panel prefetch depth 2 or 4 k-steps x {workgroups of 4 waves with 1 or 2
+ * theta in flight per CU, of 8 waves with 1}) and keeps the fastest; then, for
+ * each size bucket of n the batch holds, times that bucket's instances alone
+ * with 64- and 32-wide factorisation tiles and keeps the faster side for the
+ * bucket (eor_group_set_tile_sizes). With cache_path (may be NULL), the
+ * choices are stored in a JSON file keyed by "<gfx arch>|<size bucket of the
+ * largest n: n<=512, n<=1024, n<=2048, n<=4096, n>4096>|<single or group>"
+ * (the shape) and "<gfx arch>|<bucket>|tile" (the tile side), and existing
+ * entries are used without timing unless force != 0. A lone dataset is tuned
+ * as a one-instance group. Synchronises the stream.
  * Errors: as eor_group_loglike; EOR_ERR_ARG if the cache cannot be written.
  */
 eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *theta,

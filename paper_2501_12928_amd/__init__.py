@@ -79,6 +79,10 @@ def lib() -> ctypes.CDLL:
         L.eor_group_set_tuning.argtypes = [_P, _I32, _I32, _I32]
         L.eor_set_tuning.argtypes = [_P, _I32, _I32, _I32]
         L.eor_set_workspace_limit.argtypes = [_P, ctypes.c_size_t]
+        L.eor_set_tile_size.argtypes = [_P, _I32]
+        L.eor_get_tile_size.argtypes = [_P, ctypes.POINTER(_I32)]
+        L.eor_group_set_tile_sizes.argtypes = [_P, _P]
+        L.eor_group_tile_sizes.argtypes = [_P, _P]
         L.eor_get_tuning.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]
         L.eor_autotune.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.c_char_p, _I32, _P]
         L.eor_surrogate_create.argtypes = [ctypes.c_int, _I32, _I32, _I32, ctypes.c_uint64, _P, _P,
@@ -107,7 +111,8 @@ def lib() -> ctypes.CDLL:
         for name in ("eor_create", "eor_precompute", "eor_loglike_batch", "eor_loglike_terms",
                      "eor_export_precompute", "eor_shape", "eor_group_create", "eor_group_loglike",
                      "eor_group_set_graph", "eor_group_tuning", "eor_group_set_tuning", "eor_set_tuning",
-                     "eor_set_workspace_limit",
+                     "eor_set_workspace_limit", "eor_set_tile_size", "eor_get_tile_size",
+                     "eor_group_set_tile_sizes", "eor_group_tile_sizes",
                      "eor_get_tuning", "eor_autotune", "eor_surrogate_create",
                      "eor_surrogate_size", "eor_surrogate_params", "eor_surrogate_standardisation",
                      "eor_surrogate_train", "eor_surrogate_report", "eor_surrogate_loss_grad",
@@ -220,6 +225,15 @@ class Context:
         eor_set_workspace_limit."""
         check(lib().eor_set_workspace_limit(self._h, int(nbytes)))
 
+    def set_tile_size(self, ts: int):
+        """Side of the factorisation tiles, 64 or 32 (eor_set_tile_size)."""
+        check(lib().eor_set_tile_size(self._h, int(ts)))
+
+    def tile_size(self) -> int:
+        v = _I32()
+        check(lib().eor_get_tile_size(self._h, ctypes.byref(v)))
+        return v.value
+
     def tuning(self):
         """(prefetch stages, workgroups per CU, tiles per pass)."""
         s, w, t = _I32(), _I32(), _I32()
@@ -296,6 +310,19 @@ class Group:
 
     def set_tuning(self, stages, wg_per_cu, tiles_per_pass=1):
         check(lib().eor_group_set_tuning(self._h, stages, wg_per_cu, tiles_per_pass))
+
+    def set_tile_sizes(self, ts_per_bucket):
+        """Tile side (32 or 64) per size bucket of n: <= 512, <= 1024, <= 2048,
+        <= 4096, larger."""
+        v = np.ascontiguousarray(ts_per_bucket, dtype=np.int32)
+        if v.shape != (5,):
+            raise ValueError("five tile sides, one per size bucket")
+        check(lib().eor_group_set_tile_sizes(self._h, v.ctypes.data))
+
+    def tile_sizes(self):
+        v = np.zeros(5, dtype=np.int32)
+        check(lib().eor_group_tile_sizes(self._h, v.ctypes.data))
+        return v.tolist()
 
     def autotune(self, thetas, cache_path=None, force=False, stream=None):
         """Time every launch choice on this batch, keep the fastest and return

@@ -42,6 +42,7 @@ InstDesc inst_desc(const Context &c) {
     d.fixed_logv = c.fixed_logv;
     d.n_k = c.n_k;
     d.N = (int32_t)c.N;
+    d.ts = c.tune.ts;
     return d;
 }
 
@@ -294,6 +295,7 @@ eor_status eor_precompute(eor_ctx *ctx, int64_t m, int64_t n, const void *T, int
     EOR_TRY(hipMemcpyAsync(c.bin_scale, c.h_scale, nk1 * sizeof(double), hipMemcpyHostToDevice, s), "copy scales");
     EOR_TRY(hipMemcpyAsync(c.bin_count, c.h_count, nk1 * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy counts");
     *c.h_inst = eor::inst_desc(c);
+    c.desc_ts = c.h_inst->ts;
     EOR_TRY(hipMemcpyAsync(c.d_inst, c.h_inst, sizeof(eor::InstDesc), hipMemcpyHostToDevice, s), "copy descriptor");
 
     const double2 *Td = (const double2 *)T;
@@ -347,13 +349,25 @@ static eor_status loglike_impl(eor_ctx *ctx, int64_t B, const double *theta, dou
     p.ntask = B;
     p.counter = c.counter;
     p.Lw = c.Lw;
-    p.slot_tiles = c.slot_tiles;
+    p.slot_elems = c.slot_tiles * eor::TS2;
     p.yw = c.yw;
     p.slot_y = c.slot_y;
     p.call[0] = eor::CallDesc{theta, logL, info, terms};
     const int64_t grid = want < c.slots ? want : c.slots;
     const hipStream_t s = (hipStream_t)stream;
-    hipError_t e = c.order.enter(s);
+    hipError_t e = hipSuccess;
+    if (c.desc_ts != c.tune.ts) {
+        // the tile side changed since the descriptor was copied: restage it
+        // once the copy and the work that read it have finished
+        e = c.order.drain();
+        if (e == hipSuccess) {
+            *c.h_inst = eor::inst_desc(c);
+            e = hipMemcpyAsync(c.d_inst, c.h_inst, sizeof(eor::InstDesc), hipMemcpyHostToDevice, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "descriptor");
+        c.desc_ts = c.tune.ts;
+    }
+    e = c.order.enter(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     e = eor::launch_likelihood(p, c.tune, grid, s);
     if (e != hipSuccess) return hip_fail(e, "likelihood launch");
@@ -430,6 +444,19 @@ eor_status eor_set_tuning(eor_ctx *ctx, int32_t stages, int32_t wg_per_cu, int32
     ctx->c.tune.stages = stages;
     ctx->c.tune.wg_per_cu = wg_per_cu;
     ctx->c.tune.tiles = tiles_per_pass;
+    return EOR_OK;
+}
+
+eor_status eor_set_tile_size(eor_ctx *ctx, int32_t ts) {
+    if (!ctx) return fail(EOR_ERR_ARG, "eor_set_tile_size: ctx is NULL");
+    if (ts != 32 && ts != 64) return fail(EOR_ERR_ARG, "eor_set_tile_size: the tile side is 32 or 64");
+    ctx->c.tune.ts = ts;
+    return EOR_OK;
+}
+
+eor_status eor_get_tile_size(const eor_ctx *ctx, int32_t *ts) {
+    if (!ctx || !ts) return fail(EOR_ERR_ARG, "eor_get_tile_size: NULL argument");
+    *ts = ctx->c.tune.ts;
     return EOR_OK;
 }
 

@@ -40,7 +40,8 @@ struct InstDesc {
     double khost;              // -m ln(pi)
     double fixed_logv;         // sum over fixed coefficients of ln v_j
     int32_t n_k;
-    int32_t N;                 // tiles per side
+    int32_t N;                 // 64-wide storage tiles per side
+    int32_t ts;                // side of the factorisation tiles of L: 64 or 32
 };
 
 // Per-call arrays of one instance: theta [B x n_k], logL [B], info [B] or
@@ -62,7 +63,7 @@ struct LikeParams {
     int64_t ntask;                // < 2^31
     unsigned int *counter;        // next task; zeroed by the launch
     double2 *Lw;                  // per-slot packed tiles of L
-    int64_t slot_tiles;
+    int64_t slot_elems;           // complex entries per slot (room for 64-wide tiles)
     double2 *yw;                  // per-slot y
     int64_t slot_y;
     CallDesc call[MAX_INST];
@@ -108,9 +109,18 @@ struct StreamOrder {
 struct Tuning {
     int stages = 4;      // register prefetch depth of the panel update (2 or 4)
     int wg_per_cu = 1;   // resident workgroups (theta in flight) per CU (1 or 2)
-    int tiles = 2;       // tiles of a column updated per pass of its panel (1 or 2); 2 fills a CU
-                         // with one workgroup of eight waves, so wg_per_cu is then 1
+    int tiles = 2;       // workgroups of 4 waves (1) or 8 waves (2, which fills a CU with one
+                         // workgroup, so wg_per_cu is then 1); the tiles of a column updated per
+                         // pass of its panel are 1 or 2 with 64-wide tiles, 2 or 4 with 32-wide ones
+    int ts = 64;         // side of the factorisation tiles (64 or 32) of a lone context
 };
+
+// Size buckets of n, for the tile side chosen per bucket: n <= 512, <= 1024,
+// <= 2048, <= 4096, larger.
+constexpr int N_BUCKETS = 5;
+inline int bucket_index(int64_t n) {
+    return n <= 512 ? 0 : n <= 1024 ? 1 : n <= 2048 ? 2 : n <= 4096 ? 3 : 4;
+}
 
 // State behind an eor_ctx handle.
 struct Context {
@@ -153,6 +163,7 @@ struct Context {
     int64_t slot_tiles = 0;      // tiles per slot
     int64_t slot_y = 0;          // complex entries of y per slot
     size_t work_limit = 0;       // bytes; 0 = no limit
+    int desc_ts = 64;            // tile side in the device copy of the descriptor
     StreamOrder order;           // the last call's work on its stream
 };
 

@@ -295,17 +295,25 @@ struct Prods<2> {
 // step's are multiplied, and stored after it.
 constexpr int BF_COL = 40;  // LDS stride of a column: 32 rows + 8 pad (bf16)
 
+// Work unit u: tile u % tiles over the 32-row steps of rows [split rows_per,
+// ...), split = u / tiles (rows_per a multiple of CHUNK_ROWS). With one split
+// the tile goes to A; otherwise to its slot of `out` (FP64), and the splits
+// are added in a fixed order afterwards.
 template <int NTERM>
 __global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__restrict__ P,
-                                                        int64_t m_pad, int64_t n_pad, int64_t n,
-                                                        double2 *__restrict__ Ap) {
+                                                        int64_t m_pad, int64_t n_pad, int64_t n, int64_t tiles,
+                                                        int64_t rows_per, int splits,
+                                                        double2 *__restrict__ out) {
     constexpr int NP = 2 * NTERM;                     // planes: NTERM real, NTERM imaginary
     constexpr int BF_PANEL = NP * 64 * BF_COL;        // one panel, all planes
     constexpr int BF_LOADS = 2 * NP * 64 * 4 / 256;   // 16-byte reads per thread per step (12 or 8)
     using PR = Prods<NTERM>;
     __shared__ __align__(16) unsigned short lds[2][2 * BF_PANEL];
+    const int64_t tile = blockIdx.x % tiles, split = blockIdx.x / tiles;
+    const int64_t r0 = split * rows_per;
+    const int64_t r1 = r0 + rows_per < m_pad ? r0 + rows_per : m_pad;
     int64_t ti, tj;
-    tile_of(blockIdx.x, ti, tj);
+    tile_of(tile, ti, tj);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
     const int64_t plane = n_pad * m_pad;
     // the thread's share of a step: 16 bytes (8 rows) of one column of one
@@ -341,11 +349,11 @@ __global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__
 #pragma unroll
         for (int r = 0; r < 4; ++r) sR[cb][r] = sI[cb][r] = 0.0;
 
-    fetch(0);
+    fetch(r0);
     stash(0);
     __syncthreads();
     int buf = 0;
-    for (int64_t c0 = 0; c0 < m_pad; c0 += CHUNK_ROWS) {
+    for (int64_t c0 = r0; c0 < r1; c0 += CHUNK_ROWS) {
         f4 aR[4], aI[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
@@ -353,7 +361,7 @@ __global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__
             aI[cb] = f4{0, 0, 0, 0};
         }
         for (int64_t s0 = c0; s0 < c0 + CHUNK_ROWS; s0 += 32) {
-            const bool more = s0 + 32 < m_pad;
+            const bool more = s0 + 32 < r1;
             if (more) fetch(s0 + 32);
             bf8 ar[NTERM], ai[NTERM], nai[NTERM];
 #pragma unroll
@@ -403,7 +411,17 @@ __global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__
                 sI[cb][r] += (double)aI[cb][r];
             }
     }
-    store_tile(Ap, ti, tj, n, sR, sI, w, l16, q);
+    if (splits == 1) {
+        store_tile(out, ti, tj, n, sR, sI, w, l16, q);
+        return;
+    }
+    // partial tile, column-major: lane holds [16 w + l16][16 cb + 4 q + r]
+    double2 *pt = out + (split * tiles + tile) * TS2;
+    const int row = 16 * w + l16;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pt[(16 * cb + 4 * q + r) * TS + row] = make_double2(sR[cb][r], sI[cb][r]);
 }
 
 }  // namespace
@@ -412,6 +430,28 @@ __global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__
 void fp32_split(int64_t m_pad, int64_t N, int num_cu, int &splits, int64_t &rows_per) {
     herk_split(m_pad, N, num_cu, splits, rows_per);
     rows_per = (rows_per + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
+}
+
+// Row slices of the split-BF16 product. Its workgroups hold 120 KiB of LDS,
+// one per CU, so a round is num_cu units; the slices (whole chunks) are
+// chosen to minimise the chunk steps of the busiest CU, rounds x chunks per
+// slice, each extra slice counted as half a chunk step per unit for its
+// partial tile and its share of the reduction.
+void bf16_split(int64_t m_pad, int64_t N, int num_cu, int &splits, int64_t &rows_per) {
+    const int64_t tiles = n_tiles(N), slots = num_cu > 0 ? num_cu : 1, chunks = m_pad / CHUNK_ROWS;
+    splits = 1;
+    double best = 1e300;
+    for (int sp = 1; sp <= 8 && sp <= chunks; ++sp) {
+        const int64_t per = (chunks + sp - 1) / sp;
+        if ((sp - 1) * per >= chunks) continue;  // no empty slice
+        const int64_t rounds = (tiles * sp + slots - 1) / slots;
+        const double cost = (double)rounds * (double)per + (sp > 1 ? 0.5 * (double)rounds : 0.0);
+        if (cost < best - 1e-9) {
+            best = cost;
+            splits = sp;
+        }
+    }
+    rows_per = (chunks + splits - 1) / splits * CHUNK_ROWS;
 }
 
 size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad, int num_cu) {
@@ -423,8 +463,13 @@ size_t lowp_scratch_bytes(eor_precision prec, int64_t m, int64_t n_pad, int num_
         const size_t part = splits > 1 ? (size_t)splits * n_tiles(n_pad / TS) * TS2 * sizeof(double2) : 0;
         return (size_t)m_pad * n_pad * sizeof(float2) + part;
     }
-    if (prec == EOR_PREC_BF16X3) return (size_t)6 * m_pad * n_pad * sizeof(unsigned short);
-    if (prec == EOR_PREC_BF16X2) return (size_t)4 * m_pad * n_pad * sizeof(unsigned short);
+    if (prec == EOR_PREC_BF16X3 || prec == EOR_PREC_BF16X2) {
+        int splits;
+        int64_t rows_per;
+        bf16_split(m_pad, n_pad / TS, num_cu, splits, rows_per);
+        const size_t part = splits > 1 ? (size_t)splits * n_tiles(n_pad / TS) * TS2 * sizeof(double2) : 0;
+        return (size_t)(prec == EOR_PREC_BF16X3 ? 6 : 4) * m_pad * n_pad * sizeof(unsigned short) + part;
+    }
     return 0;
 }
 
@@ -451,14 +496,24 @@ hipError_t launch_precompute_bf16(const Context &c, const double2 *T, int64_t ld
     const int64_t m_pad = (c.m + CHUNK_ROWS - 1) / CHUNK_ROWS * CHUNK_ROWS;
     unsigned short *P = (unsigned short *)scratch;
     const dim3 sgrid((unsigned)(c.n_pad / 64), (unsigned)(m_pad / 64));
-    const dim3 hgrid((unsigned)n_tiles(c.N));
+    const int64_t tiles = n_tiles(c.N);
+    int splits;
+    int64_t rows_per;
+    bf16_split(m_pad, c.N, c.num_cu, splits, rows_per);
+    double2 *part = splits > 1 ? (double2 *)((char *)scratch + (size_t)(2 * nterm) * m_pad * c.n_pad *
+                                                                 sizeof(unsigned short))
+                               : c.A;
+    const dim3 hgrid((unsigned)(tiles * splits));
     if (nterm == 3) {
         hipLaunchKernelGGL(split_kernel<3>, sgrid, dim3(256), 0, s, T, ldT, c.m, c.n, invvar, m_pad, c.n_pad, P);
-        hipLaunchKernelGGL(herk_bf16_kernel<3>, hgrid, dim3(256), 0, s, P, m_pad, c.n_pad, c.n, c.A);
+        hipLaunchKernelGGL(herk_bf16_kernel<3>, hgrid, dim3(256), 0, s, P, m_pad, c.n_pad, c.n, tiles, rows_per,
+                           splits, part);
     } else {
         hipLaunchKernelGGL(split_kernel<2>, sgrid, dim3(256), 0, s, T, ldT, c.m, c.n, invvar, m_pad, c.n_pad, P);
-        hipLaunchKernelGGL(herk_bf16_kernel<2>, hgrid, dim3(256), 0, s, P, m_pad, c.n_pad, c.n, c.A);
+        hipLaunchKernelGGL(herk_bf16_kernel<2>, hgrid, dim3(256), 0, s, P, m_pad, c.n_pad, c.n, tiles, rows_per,
+                           splits, part);
     }
+    if (splits > 1) return launch_herk_reduce(part, tiles, splits, c.n, c.A, s);
     return hipGetLastError();
 }
 

@@ -1,12 +1,15 @@
 // Multi-instance runtime: many theta of many datasets of uneven size in one
 // persistent launch, optionally replayed from a captured HIP graph, with the
 // launch choices picked by a timing autotuner whose results persist in a
-// small JSON cache keyed by (GPU architecture, size bucket).
+// small JSON cache keyed by (GPU architecture, size bucket): the launch shape
+// for the group, and the side of the factorisation tiles (64 or 32) for each
+// bucket of instance sizes, which one launch mixes freely.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 #include <map>
 #include <new>
 #include <sstream>
@@ -32,6 +35,7 @@ struct eor_group {
     int64_t slots = 0, slot_tiles = 0, slot_y = 0;
     int64_t N_max = 0;
     eor::Tuning tune;
+    int ts_bucket[eor::N_BUCKETS] = {64, 64, 64, 64, 64};  // tile side per size bucket of n
     bool use_graph = true;
     // captured graph and what it was captured for
     hipStream_t cap_stream = nullptr;
@@ -141,14 +145,9 @@ eor_status build_tasks(eor_group &g, const int64_t *B) {
     return EOR_OK;
 }
 
-std::string bucket_of(int64_t N) {
-    const int64_t n = N * eor::TS;
-    if (n <= 512) return "n<=512";
-    if (n <= 1024) return "n<=1024";
-    if (n <= 2048) return "n<=2048";
-    if (n <= 4096) return "n<=4096";
-    return "n>4096";
-}
+const char *const kBucketName[eor::N_BUCKETS] = {"n<=512", "n<=1024", "n<=2048", "n<=4096", "n>4096"};
+
+std::string bucket_of(int64_t N) { return kBucketName[eor::bucket_index(N * eor::TS)]; }
 
 std::string arch_name(int device) {
     hipDeviceProp_t prop;
@@ -158,19 +157,28 @@ std::string arch_name(int device) {
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
-// Cache format: one entry per line,
+// Cache format: a JSON object of flat entries,
 //   "<arch>|<bucket>|<kind>": {"stages": S, "wg_per_cu": W, "tiles": P, "ms": T}
+//   "<arch>|<bucket>|tile": {"tile": 32 or 64, "ms64": T64, "ms32": T32}
+// read as every "key": {...} pair in the file, whatever its line breaks.
 std::map<std::string, std::string> read_cache(const char *path) {
     std::map<std::string, std::string> out;
     std::ifstream f(path);
-    std::string line;
-    while (std::getline(f, line)) {
-        const size_t a = line.find('"');
-        const size_t b = a == std::string::npos ? a : line.find('"', a + 1);
-        const size_t c = b == std::string::npos ? b : line.find('{', b);
-        const size_t d = c == std::string::npos ? c : line.find('}', c);
-        if (d == std::string::npos) continue;
-        out[line.substr(a + 1, b - a - 1)] = line.substr(c, d - c + 1);
+    const std::string text((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    size_t pos = 0;
+    for (;;) {
+        const size_t a = text.find('"', pos);
+        const size_t b = a == std::string::npos ? a : text.find('"', a + 1);
+        const size_t c = b == std::string::npos ? b : text.find_first_not_of(" \t\r\n:", b + 1);
+        if (c == std::string::npos) break;
+        if (text[c] != '{') {  // not an entry (e.g. a key inside a value): go on after it
+            pos = b + 1;
+            continue;
+        }
+        const size_t d = text.find('}', c);
+        if (d == std::string::npos) break;
+        out[text.substr(a + 1, b - a - 1)] = text.substr(c, d - c + 1);
+        pos = d + 1;
     }
     return out;
 }
@@ -213,7 +221,7 @@ eor::LikeParams make_params(const eor_group &g, const double *const *theta, doub
     p.ntask = g.ntask;
     p.counter = g.counter;
     p.Lw = g.Lw;
-    p.slot_tiles = g.slot_tiles;
+    p.slot_elems = g.slot_tiles * eor::TS2;
     p.yw = g.yw;
     p.slot_y = g.slot_y;
     for (size_t i = 0; i < g.inst.size(); ++i)
@@ -246,8 +254,12 @@ eor_status run_group(eor_group &g, const int64_t *B, const double *const *theta,
     hipError_t e = g.order.enter(s);
     for (size_t i = 0; i < g.inst.size() && e == hipSuccess; ++i) e = g.inst[i]->c.order.enter(s);
     if (e != hipSuccess) return eor::hip_status(e, "hipStreamWaitEvent");
-    // refresh the instance descriptors (a context may have been re-precomputed)
-    for (size_t i = 0; i < g.inst.size(); ++i) g.h_inst[i] = eor::inst_desc(g.inst[i]->c);
+    // refresh the instance descriptors (a context may have been re-precomputed),
+    // with the tile side of each instance's size bucket
+    for (size_t i = 0; i < g.inst.size(); ++i) {
+        g.h_inst[i] = eor::inst_desc(g.inst[i]->c);
+        g.h_inst[i].ts = g.ts_bucket[eor::bucket_index(g.inst[i]->c.n)];
+    }
     e = hipMemcpyAsync(g.d_inst, g.h_inst, g.inst.size() * sizeof(eor::InstDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return eor::hip_status(e, "instance descriptors");
     const int64_t resident = eor::resident_per_cu(t) * g.num_cu;
@@ -380,6 +392,21 @@ eor_status eor_group_set_tuning(eor_group *g, int32_t stages, int32_t wg_per_cu,
     return EOR_OK;
 }
 
+eor_status eor_group_set_tile_sizes(eor_group *g, const int32_t *ts_per_bucket) {
+    if (!g || !ts_per_bucket) return eor::fail_status(EOR_ERR_ARG, "eor_group_set_tile_sizes: NULL argument");
+    for (int b = 0; b < eor::N_BUCKETS; ++b)
+        if (ts_per_bucket[b] != 32 && ts_per_bucket[b] != 64)
+            return eor::fail_status(EOR_ERR_ARG, "eor_group_set_tile_sizes: each tile side is 32 or 64");
+    for (int b = 0; b < eor::N_BUCKETS; ++b) g->ts_bucket[b] = ts_per_bucket[b];
+    return EOR_OK;
+}
+
+eor_status eor_group_tile_sizes(const eor_group *g, int32_t *ts_per_bucket) {
+    if (!g || !ts_per_bucket) return eor::fail_status(EOR_ERR_ARG, "eor_group_tile_sizes: NULL argument");
+    for (int b = 0; b < eor::N_BUCKETS; ++b) ts_per_bucket[b] = g->ts_bucket[b];
+    return EOR_OK;
+}
+
 eor_status eor_group_tuning(const eor_group *g, int32_t *stages, int32_t *wg_per_cu, int32_t *tiles_per_pass,
                             int64_t *graph_launches, int64_t *graph_captures) {
     if (!g) return eor::fail_status(EOR_ERR_ARG, "eor_group_tuning: group is NULL");
@@ -402,24 +429,46 @@ eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *the
     }
     DeviceGuard dg(g->device);
     hipStream_t s = (hipStream_t)stream;
+    const int n_inst = (int)g->inst.size();
     int64_t N_max = 0;
-    for (auto *c : g->inst) N_max = std::max<int64_t>(N_max, c->c.N);
-    const std::string key = arch_name(g->device) + "|" + bucket_of(N_max) + "|" +
-                            (g->inst.size() == 1 ? "single" : "group");
+    bool present[eor::N_BUCKETS] = {false, false, false, false, false};
+    for (int i = 0; i < n_inst; ++i) {
+        N_max = std::max<int64_t>(N_max, g->inst[i]->c.N);
+        if (B[i] > 0) present[eor::bucket_index(g->inst[i]->c.n)] = true;
+    }
+    const std::string arch = arch_name(g->device);
+    const std::string key = arch + "|" + bucket_of(N_max) + "|" + (n_inst == 1 ? "single" : "group");
     std::map<std::string, std::string> cache;
     if (cache_path) cache = read_cache(cache_path);
+    // cached choices: the launch shape of this group's largest bucket, and
+    // the tile side of each bucket it holds
+    bool shape_known = false;
     if (!force && cache.count(key)) {
         eor::Tuning t;
         if (parse_entry(cache[key], t)) {
             g->tune = t;
-            return EOR_OK;
+            shape_known = true;
         }
     }
+    bool tile_known[eor::N_BUCKETS] = {false, false, false, false, false};
+    bool all_known = shape_known;
+    for (int b = 0; b < eor::N_BUCKETS; ++b) {
+        if (!present[b]) continue;
+        const std::string tk = arch + "|" + kBucketName[b] + "|tile";
+        int ts = 0;
+        if (!force && cache.count(tk) && std::sscanf(cache[tk].c_str(), "{\"tile\": %d", &ts) == 1 &&
+            (ts == 32 || ts == 64)) {
+            g->ts_bucket[b] = ts;
+            tile_known[b] = true;
+        }
+        all_known = all_known && tile_known[b];
+    }
+    if (all_known) return EOR_OK;
     // scratch outputs for the timing runs
     hipError_t e = g->order.drain();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return eor::hip_status(e, "hipStreamSynchronize");
-    for (size_t i = 0; i < g->inst.size(); ++i) {
+    for (int i = 0; i < n_inst; ++i) {
         double *o = nullptr;
         e = hipMalloc(&o, std::max<int64_t>(B[i], 1) * sizeof(double));
         if (e != hipSuccess) {
@@ -431,49 +480,73 @@ eor_status eor_autotune(eor_group *g, const int64_t *B, const double *const *the
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    eor::Tuning best;
-    double best_ms = 1e300;
     eor_status st = EOR_OK;
-    const int cand_stages[2] = {4, 2};
-    const int cand_shape[3][2] = {{1, 2}, {1, 1}, {2, 1}};  // (tiles per pass, workgroups per CU)
-    for (int a = 0; a < 2 && st == EOR_OK; ++a) {
-        for (int b = 0; b < 3 && st == EOR_OK; ++b) {
-            eor::Tuning t;
-            t.stages = cand_stages[a];
-            t.tiles = cand_shape[b][0];
-            t.wg_per_cu = cand_shape[b][1];
-            st = run_group(*g, B, theta, outs.data(), nullptr, t, false, s);  // warm-up
-            float ms_sum = 0.f;
-            for (int r = 0; r < 2 && st == EOR_OK; ++r) {
-                (void)hipEventRecord(e0, s);
-                st = run_group(*g, B, theta, outs.data(), nullptr, t, false, s);
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) st = eor::fail_status(EOR_ERR_HIP, "autotune timing");
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                ms_sum += ms;
-            }
-            const double ms = ms_sum / 2.0;
-            if (st == EOR_OK && ms < best_ms) {
-                best_ms = ms;
-                best = t;
+    // one warm-up launch, then the mean of two timed ones
+    auto time_launch = [&](const int64_t *Bv, const eor::Tuning &t) {
+        st = run_group(*g, Bv, theta, outs.data(), nullptr, t, false, s);
+        float ms_sum = 0.f;
+        for (int r = 0; r < 2 && st == EOR_OK; ++r) {
+            (void)hipEventRecord(e0, s);
+            st = run_group(*g, Bv, theta, outs.data(), nullptr, t, false, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) st = eor::fail_status(EOR_ERR_HIP, "autotune timing");
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_sum += ms;
+        }
+        return ms_sum / 2.0;
+    };
+    if (!shape_known) {
+        eor::Tuning best;
+        double best_ms = 1e300;
+        const int cand_stages[2] = {4, 2};
+        const int cand_shape[3][2] = {{1, 2}, {1, 1}, {2, 1}};  // (tiles per pass, workgroups per CU)
+        for (int a = 0; a < 2 && st == EOR_OK; ++a) {
+            for (int b = 0; b < 3 && st == EOR_OK; ++b) {
+                eor::Tuning t;
+                t.stages = cand_stages[a];
+                t.tiles = cand_shape[b][0];
+                t.wg_per_cu = cand_shape[b][1];
+                const double ms = time_launch(B, t);
+                if (st == EOR_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
             }
         }
+        if (st == EOR_OK) {
+            g->tune = best;
+            std::ostringstream v;
+            v << "{\"stages\": " << best.stages << ", \"wg_per_cu\": " << best.wg_per_cu << ", \"tiles\": "
+              << best.tiles << ", \"ms\": " << best_ms << "}";
+            cache[key] = v.str();
+        }
+    }
+    // tile side per bucket, timed on that bucket's instances alone with the
+    // chosen launch shape
+    std::vector<int64_t> Bsub(n_inst);
+    for (int b = 0; b < eor::N_BUCKETS && st == EOR_OK; ++b) {
+        if (!present[b] || tile_known[b]) continue;
+        for (int i = 0; i < n_inst; ++i) Bsub[i] = eor::bucket_index(g->inst[i]->c.n) == b ? B[i] : 0;
+        double ms_ts[2] = {0.0, 0.0};
+        const int cand_ts[2] = {64, 32};
+        for (int c = 0; c < 2 && st == EOR_OK; ++c) {
+            g->ts_bucket[b] = cand_ts[c];
+            ms_ts[c] = time_launch(Bsub.data(), g->tune);
+        }
+        if (st != EOR_OK) break;
+        g->ts_bucket[b] = ms_ts[1] < ms_ts[0] ? 32 : 64;
+        std::ostringstream v;
+        v << "{\"tile\": " << g->ts_bucket[b] << ", \"ms64\": " << ms_ts[0] << ", \"ms32\": " << ms_ts[1] << "}";
+        cache[arch + "|" + kBucketName[b] + "|tile"] = v.str();
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (double *x : outs) (void)hipFree(x);
     if (st != EOR_OK) return st;
-    g->tune = best;
     drop_graph(*g);
-    if (cache_path) {
-        std::ostringstream v;
-        v << "{\"stages\": " << best.stages << ", \"wg_per_cu\": " << best.wg_per_cu << ", \"tiles\": " << best.tiles
-          << ", \"ms\": " << best_ms << "}";
-        cache[key] = v.str();
-        if (!write_cache(cache_path, cache))
-            return eor::fail_status(EOR_ERR_ARG, std::string("eor_autotune: cannot write ") + cache_path);
-    }
+    if (cache_path && !write_cache(cache_path, cache))
+        return eor::fail_status(EOR_ERR_ARG, std::string("eor_autotune: cannot write ") + cache_path);
     return EOR_OK;
 }
 

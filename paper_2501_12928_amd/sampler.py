@@ -57,6 +57,8 @@ class Result:
     t_exact_s: float
     t_gate_s: float
     t_train_s: float
+    n_conf_checked: int = 0    # confident predictions (spread <= tau) that went to an exact call anyway
+    max_conf_err: float = 0.0  # ... their largest |mean - exact logL| (on the gate's censored scale)
 
     def posterior_moments(self):
         w = np.exp(self.logw - self.logw.max())
@@ -105,6 +107,22 @@ class Result:
         return out
 
 
+def save_result(path, r: Result):
+    """A Result as one .npz (arrays, and the scalars as JSON; no pickles)."""
+    import json
+    meta = {f.name: getattr(r, f.name) for f in dataclasses.fields(r)
+            if f.name not in ("samples", "logl", "logw")}
+    np.savez(path, samples=r.samples, logl=r.logl, logw=r.logw,
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load_result(path) -> Result:
+    import json
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(z["meta"].tobytes().decode())
+    return Result(samples=z["samples"], logl=z["logl"], logw=z["logw"], **meta)
+
+
 def _logsubexp(a, b):
     """log(exp(a) - exp(b)) for a > b."""
     return a + math.log1p(-math.exp(b - a))
@@ -133,7 +151,14 @@ class Ellipsoid:
 class NestedSampler:
     """loglike(theta [B, d] float64) -> logL [B]; gate (optional) is a
     GatedLikelihood-like object with predict(theta) -> (mean, spread) or
-    None, tau, trained, observe(theta, logL) and maybe_retrain(iteration)."""
+    None, tau, trained, reject_below(L_min), censor(logL), observe(theta,
+    logL) and maybe_retrain(iteration, L_min).
+
+    run() may stop at an iteration boundary once `time_limit` seconds have
+    passed, saving its whole state (live and dead points, pool, random
+    generators, counters, the gate's history and the surrogate's parameters)
+    to `checkpoint`; run(resume=path) continues from such a file exactly
+    where it stopped (the surrogate's Adam moments restart at zero there)."""
 
     def __init__(self, loglike, n_dim, lo, hi, n_live=500, enlarge=1.5, dlogz=0.01, batch=512,
                  seed=0, gate=None, audit_frac=0.01, max_iter=2_000_000, pool_factor=1, progress=0):
@@ -153,7 +178,8 @@ class NestedSampler:
         self.pool_factor = int(pool_factor)
         self.progress = int(progress)
         self.stats = dict(n_exact=0, n_proposed=0, n_gate_rejected=0, n_audited=0, n_false_reject=0,
-                          t_exact=0.0, t_gate=0.0)
+                          t_exact=0.0, t_gate=0.0, n_conf_checked=0, max_conf_err=0.0, n_screened=0,
+                          n_confident=0)
 
     def _exact(self, th):
         t0 = time.perf_counter()
@@ -201,7 +227,9 @@ class NestedSampler:
             t0 = time.perf_counter()
             m, sp = self.gate.predict(th)
             self.stats["t_gate"] += time.perf_counter() - t0
-            u = ~((sp <= self.gate.tau) & (m < L_min))
+            self.stats["n_screened"] += th.shape[0]
+            self.stats["n_confident"] += int(np.count_nonzero(sp <= self.gate.tau))
+            u = ~((sp <= self.gate.tau) & (m < self.gate.reject_below(L_min)))
             c = np.cumsum(u)
             if unsure + int(c[-1]) >= self.batch:
                 cut = int(np.searchsorted(c, self.batch - unsure)) + 1
@@ -220,7 +248,7 @@ class NestedSampler:
 
     def _confident_reject(self, pool, i, L_min):
         return (pool["mean"] is not None and pool["spread"][i] <= self.gate.tau
-                and pool["mean"][i] < L_min)
+                and pool["mean"][i] < self.gate.reject_below(L_min))
 
     def _next_valid(self, pool, L_min):
         """Index of the next proposal of the pool with exact logL > L_min,
@@ -244,21 +272,94 @@ class NestedSampler:
             idx = [j for j in range(i, th.shape[0])
                    if np.isnan(L[j]) and not self._confident_reject(pool, j, L_min)]
             L[idx] = self._exact(th[idx])
+            if pool["mean"] is not None:
+                # the surrogate's error where it was confident (spread <= tau) but
+                # not below the threshold, so the point went to the exact call
+                conf = [j for j in idx if pool["spread"][j] <= self.gate.tau]
+                if conf:
+                    err = np.abs(pool["mean"][conf] - self.gate.censor(L[conf]))
+                    self.stats["n_conf_checked"] += len(conf)
+                    self.stats["max_conf_err"] = max(self.stats["max_conf_err"], float(np.max(err)))
         return None
 
-    def run(self) -> Result:
-        t_start = time.perf_counter()
-        d, n = self.d, self.n_live
-        live = self.lo + (self.hi - self.lo) * self.rng.uniform(size=(n, d))
-        live_L = self._exact(live)
-        dead, dead_L, dead_lnw = [], [], []
-        logz = -np.inf
-        ln_x_prev = 0.0
+    def _save(self, path, st):
+        """Everything run() needs to continue, in one .npz (no pickles:
+        arrays, and the scalars as JSON)."""
+        import json
+        pool = st["pool"]
+        arrays = dict(live=st["live"], live_L=st["live_L"], dead=np.array(st["dead"]).reshape(-1, self.d),
+                      dead_L=np.array(st["dead_L"]), dead_lnw=np.array(st["dead_lnw"]),
+                      audit_th=np.array([a for a, _ in self._audits]).reshape(-1, self.d),
+                      audit_L=np.array([b for _, b in self._audits]))
+        meta = dict(logz=float(st["logz"]), ln_x_prev=float(st["ln_x_prev"]), it=int(st["it"]),
+                    elapsed=float(st["elapsed"]), t_train0=float(st["t_train0"]), stats=self.stats,
+                    rng=self.rng.bit_generator.state, audit_rng=self.audit_rng.bit_generator.state,
+                    pool=None if pool is None else dict(pos=int(pool["pos"]), gated=pool["mean"] is not None))
+        if pool is not None:
+            arrays["pool_th"] = pool["th"]
+            arrays["pool_L"] = pool["L"]
+            if pool["mean"] is not None:
+                arrays["pool_mean"] = pool["mean"]
+                arrays["pool_spread"] = pool["spread"]
+        if self.gate is not None:
+            g_arrays, g_meta = self.gate.state()
+            arrays.update({"gate_" + k: v for k, v in g_arrays.items()})
+            meta["gate"] = g_meta
+        arrays["meta"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
+        np.savez(path, **arrays)
+
+    def _load(self, path):
+        import json
+        z = np.load(path, allow_pickle=False)
+        meta = json.loads(z["meta"].tobytes().decode())
+        self.stats = meta["stats"]
+        self.rng.bit_generator.state = meta["rng"]
+        self.audit_rng.bit_generator.state = meta["audit_rng"]
+        self._audits = [(z["audit_th"][k].copy(), float(z["audit_L"][k])) for k in range(z["audit_L"].shape[0])]
         pool = None
-        self._audits = []
-        it = 0
-        t_train0 = self.gate.train_seconds if self.gate is not None else 0.0
+        if meta["pool"] is not None:
+            pool = {"th": z["pool_th"], "L": z["pool_L"].copy(), "pos": meta["pool"]["pos"],
+                    "mean": z["pool_mean"] if meta["pool"]["gated"] else None,
+                    "spread": z["pool_spread"] if meta["pool"]["gated"] else None}
+        if self.gate is not None:
+            self.gate.set_state({k[5:]: z[k] for k in z.files if k.startswith("gate_")}, meta["gate"])
+        return dict(live=z["live"].copy(), live_L=z["live_L"].copy(), dead=list(z["dead"]),
+                    dead_L=list(z["dead_L"]), dead_lnw=list(z["dead_lnw"]), logz=meta["logz"],
+                    ln_x_prev=meta["ln_x_prev"], pool=pool, it=meta["it"], elapsed=meta["elapsed"],
+                    t_train0=meta["t_train0"])
+
+    def run(self, time_limit=None, checkpoint=None, resume=None):
+        """The nested-sampling run as a Result; None if this call stopped
+        after `time_limit` seconds of its own (its state then saved to
+        `checkpoint`; every call makes at least one iteration)."""
+        t_start = t_call = time.perf_counter()
+        d, n = self.d, self.n_live
+        if resume is not None:
+            st = self._load(resume)
+            live, live_L = st["live"], st["live_L"]
+            dead, dead_L, dead_lnw = st["dead"], st["dead_L"], st["dead_lnw"]
+            logz, ln_x_prev, pool, it = st["logz"], st["ln_x_prev"], st["pool"], st["it"]
+            t_start -= st["elapsed"]
+            t_train0 = st["t_train0"]
+        else:
+            live = self.lo + (self.hi - self.lo) * self.rng.uniform(size=(n, d))
+            live_L = self._exact(live)
+            dead, dead_L, dead_lnw = [], [], []
+            logz = -np.inf
+            ln_x_prev = 0.0
+            pool = None
+            self._audits = []
+            it = 0
+            t_train0 = self.gate.train_seconds if self.gate is not None else 0.0
+            if self.gate is not None:
+                self.gate.maybe_retrain(it, float(np.min(live_L)))
+        it_call = it
         while it < self.max_iter:
+            if time_limit is not None and it > it_call and time.perf_counter() - t_call > time_limit:
+                self._save(checkpoint, dict(live=live, live_L=live_L, dead=dead, dead_L=dead_L,
+                                            dead_lnw=dead_lnw, logz=logz, ln_x_prev=ln_x_prev, pool=pool,
+                                            it=it, elapsed=time.perf_counter() - t_start, t_train0=t_train0))
+                return None
             worst = int(np.argmin(live_L))
             L_min = float(live_L[worst])
             ln_x = -(it + 1) / n
@@ -277,11 +378,12 @@ class NestedSampler:
             live[worst] = pool["th"][j]
             live_L[worst] = pool["L"][j]
             if self.gate is not None:
-                self.gate.maybe_retrain(it)
+                self.gate.maybe_retrain(it, float(np.min(live_L)))
             if self.progress and it % self.progress == 0:
                 import sys
                 print(f"ns: iteration {it} ln Z {logz:.3f} L_min {L_min:.3f} exact {self.stats['n_exact']} "
-                      f"gate-rejected {self.stats['n_gate_rejected']} {time.perf_counter() - t_start:.1f}s",
+                      f"gate-rejected {self.stats['n_gate_rejected']} screened {self.stats['n_screened']} "
+                      f"confident {self.stats['n_confident']} {time.perf_counter() - t_start:.1f}s",
                       file=sys.stderr, flush=True)
             # stop when the live points can no longer change ln Z by dlogz
             if np.logaddexp(logz, float(np.max(live_L)) + ln_x) - logz < self.dlogz:
@@ -310,27 +412,44 @@ class NestedSampler:
                       n_false_reject=st["n_false_reject"],
                       n_retrain=self.gate.n_train if self.gate is not None else 0,
                       wall_s=time.perf_counter() - t_start, t_exact_s=st["t_exact"], t_gate_s=st["t_gate"],
-                      t_train_s=(self.gate.train_seconds - t_train0) if self.gate is not None else 0.0)
+                      t_train_s=(self.gate.train_seconds - t_train0) if self.gate is not None else 0.0,
+                      n_conf_checked=st["n_conf_checked"], max_conf_err=st["max_conf_err"])
 
 
 class GatedLikelihood:
     """The surrogate gate for NestedSampler: keeps the exact evaluations it
-    sees, (re)trains the surrogate on the most recent ones near the current
-    threshold, and decides which proposals need an exact call. Until the
-    first training every proposal is evaluated exactly.
+    sees, (re)trains the surrogate on the most recent ones, and decides which
+    proposals need an exact call. Until the first training (once
+    `first_train` exact evaluations have been seen: the initial prior draws
+    and the early proposals) every proposal is evaluated exactly.
 
-    Nested-sampling rejections lie just below the threshold L_min (the
-    proposals come from a tight ellipsoid around the live points), so the
-    surrogate must be accurate there: retraining uses the last `window`
-    exact evaluations with logL >= L_min - margin, standardised on that
-    window, starting from the previous parameters.
+    Nested-sampling rejections lie below the threshold L_min, so the
+    surrogate must be accurate there. Two ways to train for it:
+
+    - band=None: retraining uses the last `window` exact evaluations with
+      logL >= L_min - margin, standardised on that window, starting from the
+      previous parameters.
+    - band=(below, above): the network is trained on the last `window` exact
+      evaluations with logL censored to the band [L_ref - below, L_ref +
+      above] around the threshold L_ref at training time. The gate's decision
+      only asks whether a proposal lies below the threshold, and censoring
+      keeps that answer wherever the band reaches: a proposal far below
+      predicts the floor, which is below every later threshold. The flat
+      parts are easy to fit, so the ensemble agrees there (small spread) even
+      early in the run, when logL spans thousands of units over the live
+      points and its uncensored fit could never reach a spread of tau. Above
+      the band the network predicts the band's top, so a rejection is
+      trusted only below min(L_min, top - guard), a stricter rule than the
+      plain one; the band is re-centred by retraining once L_min has climbed
+      half its upper width (at most once per `stale_gap` iterations).
 
     surrogate: an object with train(theta, logL, ...) and gate(theta, L_min,
     tau) -> (mean, spread, decision) (paper_2501_12928_amd.Surrogate, or any
     stand-in with that interface)."""
 
     def __init__(self, surrogate, tau=0.05, first_train=100_000, retrain_every=0, window=100_000,
-                 margin=np.inf, train_kwargs=None, retrain_kwargs=None):
+                 margin=np.inf, train_kwargs=None, retrain_kwargs=None, band=None, guard=1.0, stale_gap=250,
+                 whiten=False, cold=False, seed=0):
         self.s = surrogate
         self.tau = float(tau)
         self.first_train = int(first_train)
@@ -348,45 +467,137 @@ class GatedLikelihood:
         self.n_train = 0
         self.train_seconds = 0.0
         self._last_iter = 0
-        self.L_min = -np.inf
+        self.band = None if band is None else (float(band[0]), float(band[1]))
+        self.guard = float(guard)
+        self.stale_gap = int(stale_gap)
+        self.L_ref = -np.inf   # threshold at the last training
+        self.floor = -np.inf   # band the network was trained on
+        self.cap = np.inf
+        # whiten: the network sees z = (theta - mid) / half, with mid and half
+        # from the bounding box of its training inputs (enlarged by a quarter),
+        # so the live region, however small in the prior box, spans [-1, 1];
+        # the surrogate's own box must then be [-1, 1]. cold: every training
+        # starts from fresh He-normal weights (needed when the map changes).
+        self.whiten = bool(whiten)
+        self.cold = bool(cold)
+        self.seed = int(seed)
+        self.mid = None
+        self.half = None
+
+    def _map(self, th):
+        return (th - self.mid) / self.half if self.whiten else th
+
+    def _reinit(self):
+        """Fresh He-normal weights N(0, 2 / fan_in), zero biases, for every
+        member (the flat layout W1 [H, n_in], b1, W2 [H, H], b2, W3 [H], b3)."""
+        rng = np.random.default_rng([self.seed, self.n_train])
+        M, P = self.s.M, self.s.P
+        n_in, H = self.s.n_in, self.s.H
+        p = np.zeros((M, P), dtype=np.float32)
+        for z in range(M):
+            o = 0
+            p[z, o:o + H * n_in] = rng.standard_normal(H * n_in) * math.sqrt(2.0 / n_in)
+            o += H * n_in + H
+            p[z, o:o + H * H] = rng.standard_normal(H * H) * math.sqrt(2.0 / H)
+            o += H * H + H
+            p[z, o:o + H] = rng.standard_normal(H) * math.sqrt(2.0 / H)
+        self.s.set_params(p)
 
     def observe(self, th, L):
-        if L.size:
-            self.L_min = max(self.L_min, float(np.min(L)))
         ok = np.isfinite(L)
         self._th.append(np.asarray(th)[ok])
         self._L.append(np.asarray(L)[ok])
         self._count += int(ok.sum())
-        if not self.trained and self._count >= self.first_train:
-            self._train()
 
-    def _train(self):
+    def censor(self, L):
+        """logL on the scale the network was trained on."""
+        return np.clip(L, self.floor, self.cap) if self.band is not None else L
+
+    def reject_below(self, L_min):
+        """Threshold under which a confident prediction is rejected."""
+        return L_min if self.band is None else min(L_min, self.cap - self.guard)
+
+    def _train(self, L_min):
         th = np.concatenate(self._th)
         L = np.concatenate(self._L)
         keep = max(self.window * 4, 1)
         th, L = th[-keep:], L[-keep:]           # bounded history
         self._th, self._L = [th], [L]
-        near = L >= self.L_min - self.margin
-        if np.count_nonzero(near) >= 256:
-            th, L = th[near], L[near]
-        th, L = th[-self.window:], L[-self.window:]
+        if self.band is None:
+            near = L >= L_min - self.margin
+            if np.count_nonzero(near) >= 256:
+                th, L = th[near], L[near]
+            th, y = th[-self.window:], L[-self.window:]
+        else:
+            self.floor, self.cap = L_min - self.band[0], L_min + self.band[1]
+            th, y = th[-self.window:], np.clip(L[-self.window:], self.floor, self.cap)
         t0 = time.perf_counter()
-        self.s.train(th, L, **(self.retrain_kwargs if self.trained else self.train_kwargs))
+        if self.whiten:
+            lo, hi = th.min(axis=0), th.max(axis=0)
+            self.mid = 0.5 * (lo + hi)
+            self.half = np.maximum(0.625 * (hi - lo), 1e-12)
+        if self.cold and self.trained:
+            self._reinit()
+        self.s.train(self._map(th), y, **(self.retrain_kwargs if self.trained and not self.cold
+                                           else self.train_kwargs))
         self.train_seconds += time.perf_counter() - t0
         self.trained = True
         self.n_train += 1
+        self.L_ref = L_min
 
-    def maybe_retrain(self, it):
-        if self.trained and self.retrain_every > 0 and it - self._last_iter >= self.retrain_every:
+    def maybe_retrain(self, it, L_min):
+        """Called at every iteration with the threshold in force: the first
+        training, the periodic retraining and the band's re-centring."""
+        if not self.trained:
+            if self._count >= self.first_train:
+                self._last_iter = it
+                self._train(L_min)
+            return
+        due = self.retrain_every > 0 and it - self._last_iter >= self.retrain_every
+        stale = (self.band is not None and it - self._last_iter >= self.stale_gap
+                 and L_min > self.L_ref + 0.5 * self.band[1])
+        if due or stale:
             self._last_iter = it
-            self._train()
+            self._train(L_min)
+
+    def state(self):
+        """(arrays, scalars) of the gate for a checkpoint, the surrogate's
+        parameters and standardisation included."""
+        th = np.concatenate(self._th) if self._th else np.zeros((0, 0))
+        L = np.concatenate(self._L) if self._L else np.zeros(0)
+        arrays = {"th": th, "L": L}
+        meta = dict(count=self._count, trained=self.trained, n_train=self.n_train,
+                    train_seconds=self.train_seconds, last_iter=self._last_iter, L_ref=float(self.L_ref),
+                    floor=float(self.floor), cap=float(self.cap),
+                    mid=None if self.mid is None else self.mid.tolist(),
+                    half=None if self.half is None else self.half.tolist())
+        if self.trained:
+            p = self.s.get_params()
+            arrays["params"] = p.cpu().numpy() if hasattr(p, "cpu") else np.asarray(p)
+            meta["standardisation"] = [float(v) for v in self.s.standardisation()]
+        return arrays, meta
+
+    def set_state(self, arrays, meta):
+        self._th = [arrays["th"].copy()] if arrays["th"].size else []
+        self._L = [arrays["L"].copy()] if arrays["L"].size else []
+        self._count = int(meta["count"])
+        self.trained = bool(meta["trained"])
+        self.n_train = int(meta["n_train"])
+        self.train_seconds = float(meta["train_seconds"])
+        self._last_iter = int(meta["last_iter"])
+        self.L_ref, self.floor, self.cap = float(meta["L_ref"]), float(meta["floor"]), float(meta["cap"])
+        self.mid = None if meta.get("mid") is None else np.array(meta["mid"])
+        self.half = None if meta.get("half") is None else np.array(meta["half"])
+        if self.trained:
+            self.s.set_params(arrays["params"])
+            self.s.standardisation(np.array(meta["standardisation"]))
 
     def predict(self, th):
         """(mean, spread) of the ensemble for a pool of proposals, or None
         before the first training."""
         if not self.trained:
             return None
-        m, sp, _ = self.s.gate(th, -np.inf, self.tau)
+        m, sp, _ = self.s.gate(np.ascontiguousarray(self._map(th)), -np.inf, self.tau)
         as_np = (lambda x: x.cpu().numpy()) if hasattr(m, "cpu") else np.asarray
         return as_np(m), as_np(sp)
 
@@ -403,7 +614,8 @@ def exact_gpu(ctx):
 
 def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0.05, first_train=100_000,
                         retrain_every=0, window=100_000, margin=np.inf, train_cfg=None, batch=512, dlogz=0.01,
-                        audit_frac=0.01, pool_factor=1, progress=0, retrain_cfg=None):
+                        audit_frac=0.01, pool_factor=1, progress=0, retrain_cfg=None, band=None, guard=1.0,
+                        stale_gap=250):
     """The same nested-sampling run without and with the surrogate gate
     (same seed), and the comparison: evidence, per-bin posterior mean and
     standard deviation, exact calls avoided and wall-clock speedup."""
@@ -413,15 +625,26 @@ def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0
     gate = GatedLikelihood(surrogate, tau=tau, first_train=first_train, retrain_every=retrain_every,
                            window=window, margin=margin,
                            train_kwargs={"cfg": train_cfg} if train_cfg is not None else {},
-                           retrain_kwargs={"cfg": retrain_cfg} if retrain_cfg is not None else None)
+                           retrain_kwargs={"cfg": retrain_cfg} if retrain_cfg is not None else None,
+                           band=band, guard=guard, stale_gap=stale_gap)
     gated = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
                           gate=gate, audit_frac=audit_frac, pool_factor=pool_factor, progress=progress).run()
+    return plain, gated, compare_runs(plain, gated, n_live)
+
+
+def compare_runs(plain, gated, n_live):
+    """Agreement and cost of a gated run against the plain one: evidence
+    (tolerance 3 sqrt(H / n_live)), per-bin posterior means in posterior
+    standard deviations, exact calls avoided, wall-clock speedup."""
     m1, s1 = plain.posterior_moments()
     m2, s2 = gated.posterior_moments()
-    return plain, gated, {
+    return {
         "logz_plain": plain.logz, "logz_gated": gated.logz,
         "logz_tolerance": 3.0 * math.sqrt(plain.information / n_live),
         "max_dmean_over_sigma": float(np.max(np.abs(m1 - m2) / s1)),
+        "proposals_plain": plain.n_proposed, "proposals_gated": gated.n_proposed,
+        "proposals_per_s_plain": plain.n_proposed / plain.wall_s,
+        "proposals_per_s_gated": gated.n_proposed / gated.wall_s,
         "max_dstd_rel": float(np.max(np.abs(s2 / s1 - 1.0))),
         "exact_calls_plain": plain.n_exact, "exact_calls_gated": gated.n_exact,
         "exact_calls_avoided_frac": 1.0 - gated.n_exact / plain.n_exact,
@@ -431,4 +654,5 @@ def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0
         "speedup": plain.wall_s / gated.wall_s,
         "train_s": gated.t_train_s, "gate_s": gated.t_gate_s, "retrains": gated.n_retrain,
         "iterations_plain": plain.iterations, "iterations_gated": gated.iterations,
+        "confident_checked": gated.n_conf_checked, "confident_max_err": gated.max_conf_err,
     }

@@ -10,12 +10,14 @@ def have_gpu():
         return False
 
 
-def run_instance(inst, theta=None, prec="fp64", terms=False, tuning=None):
+def run_instance(inst, theta=None, prec="fp64", terms=False, tuning=None, ts=None):
     import torch
     import paper_2501_12928_amd as eor
     ctx = eor.Context(0)
     if tuning is not None:
         ctx.set_tuning(*tuning)
+    if ts is not None:
+        ctx.set_tile_size(ts)
     ctx.precompute(torch.from_numpy(inst.T).cuda(), torch.from_numpy(inst.noise_var).cuda(),
                    torch.from_numpy(inst.d).cuda(), inst.n_k, inst.bin_of, inst.fixed_var,
                    inst.bin_scale, prec=prec)

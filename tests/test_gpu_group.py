@@ -184,11 +184,60 @@ def test_autotune_and_cache(problem, tmp_path):
     cache.write_text(json.dumps(data))
     g2 = eor.Group(ctxs)
     assert g2.autotune(_thetas(insts), cache_path=cache) == (2, 1, 2)
+    # the tile side of the one bucket this batch holds (n <= 512) is cached too
+    tk = [k for k in data if k.endswith("|n<=512|tile")]
+    assert len(tk) == 1 and data[tk[0]]["tile"] in (32, 64)
+    assert g.tile_sizes()[0] == data[tk[0]]["tile"]
+    assert g2.tile_sizes()[0] == data[tk[0]]["tile"]
+    # a cached tile side is taken as it stands
+    data[tk[0]] = {"tile": 96 - data[tk[0]]["tile"], "ms64": 1.0, "ms32": 1.0}
+    cache.write_text(json.dumps(data))
+    g3 = eor.Group(ctxs)
+    g3.autotune(_thetas(insts), cache_path=cache)
+    assert g3.tile_sizes()[0] == data[tk[0]]["tile"]
+    outs, _ = g3.loglike(_thetas(insts))
+    torch.cuda.synchronize()
+    _check_all(outs, refs)
     outs, _ = g2.loglike(_thetas(insts))
     torch.cuda.synchronize()
     _check_all(outs, refs)
     g.close()
     g2.close()
+    g3.close()
+
+
+def test_group_mixed_tile_sides(orc):
+    """Instances in three size buckets, factored with 32-wide tiles in two of
+    them and 64-wide in the third, in one launch (eager and from a graph):
+    each matches the oracle, and each equals a lone context with the same
+    tile side bit for bit."""
+    import paper_2501_12928_amd as eor
+    import torch
+    shapes = [(700, 5, 4), (130, 9, 3), (1100, 4, 6), (200, 6, 2)]   # buckets 1, 0, 2, 0
+    insts, ctxs = _contexts(shapes, seed=300)
+    refs = [orc.loglike_instance(i)[0] for i in insts]
+    sides = [32, 64, 32, 64, 64]
+    g = eor.Group(ctxs)
+    g.set_tile_sizes(sides)
+    assert g.tile_sizes() == sides
+    with pytest.raises(eor.EorError):
+        g.set_tile_sizes([32, 64, 16, 64, 64])
+    for graph in (False, True):
+        g.set_graph(graph)
+        print(f"gpu: group with mixed tile sides, graph {graph}", flush=True)
+        outs, infos = g.loglike(_thetas(insts))
+        torch.cuda.synchronize()
+        assert all(bool((i == 0).all()) for i in infos)
+        _check_all(outs, refs)
+    for inst, ctx, out in zip(insts, ctxs, outs):
+        ctx.set_tile_size(32 if inst.n <= 512 else (64 if inst.n <= 1024 else 32))
+        single, _ = ctx.loglike_batch(torch.from_numpy(inst.theta).cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(single, out)
+        ctx.set_tile_size(64)
+    g.close()
+    for c in ctxs:
+        c.close()
 
 
 def test_group_argument_errors(problem):
@@ -235,15 +284,18 @@ def test_uneven_subband_workload_sampled(orc):
             assert inst.digest() == gold[str(idx)]["digest"]
         ctxs.append(ctx)
         thetas.append(torch.from_numpy(inst.theta).cuda())
-    print("gpu: 48-instance workload, group launch", flush=True)
     g = eor.Group(ctxs)
-    outs, infos = g.loglike(thetas)
-    torch.cuda.synchronize()
-    assert all(bool((i == 0).all()) for i in infos)
-    for k, v in gold.items():
-        got = outs[int(k)].cpu().numpy()[:len(v["logL"])]
-        ref = np.array(v["logL"])
-        assert np.all(np.abs(got - ref) <= tol(ref)), (k, np.abs(got - ref).max())
+    for sides in ([64] * 5, [32] * 5, [32, 32, 64, 64, 64]):
+        print(f"gpu: 48-instance workload, group launch, tile sides {sides}", flush=True)
+        g.set_tile_sizes(sides)
+        outs, infos = g.loglike(thetas)
+        torch.cuda.synchronize()
+        assert all(bool((i == 0).all()) for i in infos)
+        for k, v in gold.items():
+            got = outs[int(k)].cpu().numpy()[:len(v["logL"])]
+            ref = np.array(v["logL"])
+            assert np.all(np.abs(got - ref) <= tol(ref)), (k, np.abs(got - ref).max())
+            assert np.all(np.abs(got - ref) <= 1e-10 * np.abs(ref)), (k, np.abs(got - ref).max())
     g.close()
     for c in ctxs:
         c.close()

@@ -60,6 +60,7 @@ def test_precompute_products(orc):
     assert abs(gK0 - K0) <= 1e-13 * abs(K0)
 
 
+@pytest.mark.parametrize("ts", [64, 32])
 @pytest.mark.parametrize("m,n,n_k,n_eor", [
     (5, 1, 1, 1),        # one coefficient
     (80, 63, 2, 50),     # just under one tile
@@ -70,11 +71,11 @@ def test_precompute_products(orc):
     (600, 384, 1, 384),  # six tiles, one bin
     (700, 300, 7, 0),    # every coefficient fixed (no bins used)
 ])
-def test_ragged_shapes(orc, m, n, n_k, n_eor):
+def test_ragged_shapes(orc, m, n, n_k, n_eor, ts):
     inst = synth.small(seed=m + n, m=m, n=n, n_k=n_k, n_eor=n_eor, n_theta=9)
     ref, rinfo = orc.loglike_instance(inst)
-    _say(f"gpu: ragged m={m} n={n} n_k={n_k} n_eor={n_eor}")
-    got, info = run_instance(inst)
+    _say(f"gpu: ragged m={m} n={n} n_k={n_k} n_eor={n_eor} tile {ts}")
+    got, info = run_instance(inst, ts=ts)
     np.testing.assert_array_equal(info, rinfo)
     _check(got, ref)
 
@@ -106,20 +107,22 @@ def test_terms_match_oracle(orc):
 TUNINGS = [(4, 2, 1), (2, 2, 1), (4, 1, 1), (4, 1, 2), (2, 1, 2)]
 
 
+@pytest.mark.parametrize("ts", [64, 32])
 @pytest.mark.parametrize("m,n,n_k", [
-    (300, 130, 4),   # 3 tiles: 3, 2, 1 units per column
+    (300, 130, 4),   # 3 tiles of 64: 3, 2, 1 units per column (6 tiles of 32)
     (520, 257, 5),   # 5 tiles, ragged by one
-    (900, 700, 6),   # 11 tiles
+    (900, 700, 6),   # 11 tiles (22 of 32)
 ])
-def test_launch_choices_agree(orc, m, n, n_k):
+def test_launch_choices_agree(orc, m, n, n_k, ts):
     """Every launch choice meets the bar, and all give the same bits: the
-    tile updates sum in the same order whichever group computes them."""
+    tile updates sum in the same order whichever group computes them (with
+    32-wide tiles, two or four groups per workgroup)."""
     inst = synth.small(seed=m + 3 * n, m=m, n=n, n_k=n_k, n_theta=12)
     ref, rinfo = orc.loglike_instance(inst)
     outs = []
     for t in TUNINGS:
-        _say(f"gpu: n={n} tuning {t}")
-        got, info = run_instance(inst, tuning=t)
+        _say(f"gpu: n={n} tuning {t} tile {ts}")
+        got, info = run_instance(inst, tuning=t, ts=ts)
         assert np.all(info == 0) and np.all(rinfo == 0)
         _check(got, ref)
         outs.append(got)
@@ -131,6 +134,12 @@ def test_tuning_arguments():
     import paper_2501_12928_amd as eor
     ctx = eor.Context(0)
     assert ctx.tuning() == (4, 1, 2)
+    assert ctx.tile_size() == 64
+    for bad in (0, 16, 48, 128):
+        with pytest.raises(eor.EorError):
+            ctx.set_tile_size(bad)
+    ctx.set_tile_size(32)
+    assert ctx.tile_size() == 32
     for bad in [(3, 1, 1), (4, 3, 1), (4, 2, 2), (4, 1, 3), (0, 0, 0)]:
         with pytest.raises(eor.EorError):
             ctx.set_tuning(*bad)
@@ -140,8 +149,8 @@ def test_tuning_arguments():
     ctx.close()
 
 
-@pytest.mark.parametrize("tuning", [None, (4, 2, 1)])
-def test_failures_reported_per_theta(orc, tuning):
+@pytest.mark.parametrize("tuning,ts", [(None, 64), ((4, 2, 1), 64), (None, 32), ((2, 2, 1), 32)])
+def test_failures_reported_per_theta(orc, tuning, ts):
     """Non-finite theta -> info -1; a NaN column of T -> pivot failure at
     that column (1-based), exactly as the oracle reports it; the rest of
     the batch is unaffected."""
@@ -151,8 +160,8 @@ def test_failures_reported_per_theta(orc, tuning):
     th[3, 0] = np.inf
     th[4, 1] = 400.0     # 10^400 overflows: prior variance not finite
     ref, rinfo = orc.loglike_instance(inst, theta=th)
-    _say(f"gpu: failure codes, tuning {tuning}")
-    got, info = run_instance(inst, theta=th, tuning=tuning)
+    _say(f"gpu: failure codes, tuning {tuning} tile {ts}")
+    got, info = run_instance(inst, theta=th, tuning=tuning, ts=ts)
     np.testing.assert_array_equal(info, rinfo)
     np.testing.assert_array_equal(info, [0, -1, 0, -1, -1])
     assert np.all(got[info != 0] == -np.inf)
@@ -162,7 +171,7 @@ def test_failures_reported_per_theta(orc, tuning):
     bad.T = bad.T.copy()
     bad.T[:, 70] = np.nan
     ref, rinfo = orc.loglike_instance(bad)
-    got, info = run_instance(bad, tuning=tuning)
+    got, info = run_instance(bad, tuning=tuning, ts=ts)
     np.testing.assert_array_equal(rinfo, [71, 71, 71])
     np.testing.assert_array_equal(info, rinfo)
     assert np.all(got == -np.inf)
@@ -281,6 +290,17 @@ def test_metric_workload():
     torch.cuda.synchronize()
     np.testing.assert_array_equal(info.cpu().numpy(), np.array(g["extra_info"]))
     _check(L.cpu().numpy(), np.array(g["extra_logL"]))
+    # 32-wide tiles: the same batch, the same 40 oracle values
+    _say("gpu: metric workload with 32-wide tiles")
+    ctx.set_tile_size(32)
+    L32, info = ctx.loglike_batch(th)
+    Lx, infox = ctx.loglike_batch(torch.from_numpy(xt).cuda())
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0) and np.all(infox.cpu().numpy() == 0)
+    L32 = L32.cpu().numpy()
+    _check(L32[idx], np.array(g["logL"]))
+    _check(Lx.cpu().numpy(), np.array(g["extra_logL"]))
+    assert np.max(np.abs(L32 - base) / np.abs(base)) < 1e-11
     ctx.close()
 
 

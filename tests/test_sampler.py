@@ -124,3 +124,84 @@ def test_ellipsoid_bounds_and_volume():
     assert np.all(rx <= 1.0 + 1e-9)
     # uniform in the ball: P(r < 0.5) = 0.5^3
     assert abs(np.mean(rx < 0.5) - 0.125) < 0.01
+
+
+class CensoredSurrogate:
+    """Stand-in that learns the censoring band it is trained on: its mean is
+    the exact logL clipped to [min(y), max(y)] of the last training targets,
+    with zero spread; parameters are the band itself."""
+
+    def __init__(self):
+        self.lo, self.hi = -np.inf, np.inf
+        self.n_trained = 0
+
+    def train(self, th, y, **kw):
+        self.lo, self.hi = float(np.min(y)), float(np.max(y))
+        self.n_trained += 1
+
+    def gate(self, th, L_min, tau):
+        m = np.clip(gauss_loglike(th), self.lo, self.hi)
+        s = np.zeros(th.shape[0])
+        return m, s, np.where(m < L_min, 0, 1).astype(np.int32)
+
+    def get_params(self):
+        return np.array([[self.lo, self.hi]])
+
+    def set_params(self, p):
+        self.lo, self.hi = float(p[0][0]), float(p[0][1])
+
+    def standardisation(self, mean_std=None):
+        return np.array([0.0, 1.0]) if mean_std is None else mean_std
+
+
+def test_censored_band_gate_keeps_the_answer():
+    """Trained on logL censored to a band around the threshold, a surrogate
+    that is exact on that scale rejects only proposals below the threshold
+    (audits find no false rejection), keeps evidence and posterior, and
+    avoids exact calls: the floor catches every proposal far below, whatever
+    the distance."""
+    d = 4
+    plain = NestedSampler(gauss_loglike, d, LO, HI, n_live=300, dlogz=0.01, batch=256, seed=5).run()
+    sur = CensoredSurrogate()
+    gate = GatedLikelihood(sur, tau=0.05, first_train=1500, retrain_every=2000, window=3000,
+                           band=(2.0, 3.0), guard=0.5, stale_gap=50)
+    gated = NestedSampler(gauss_loglike, d, LO, HI, n_live=300, dlogz=0.01, batch=256, seed=5,
+                          gate=gate, audit_frac=0.2).run()
+    assert sur.n_trained > 3          # the band was re-centred as the threshold climbed
+    assert gated.n_false_reject == 0 and gated.n_audited > 50
+    assert abs(gated.logz - plain.logz) < 3 * math.sqrt(plain.logz_err ** 2 + gated.logz_err ** 2)
+    m1, s1 = plain.posterior_moments()
+    m2, _ = gated.posterior_moments()
+    assert np.all(np.abs(m1 - m2) < 0.15 * s1)
+    assert gated.n_exact < 0.8 * plain.n_exact
+    np.testing.assert_array_equal(gated.logl, gauss_loglike(gated.samples))
+    assert gated.n_conf_checked > 0
+    # the stricter rule never rejects above the band's top minus the guard
+    assert gate.reject_below(gate.cap + 10.0) == gate.cap - 0.5
+    assert gate.reject_below(gate.cap - 5.0) == gate.cap - 5.0
+
+
+def test_checkpoint_and_resume_reproduce_the_run(tmp_path):
+    """A run stopped at a time limit and resumed from its checkpoint, over and
+    over, ends with the same samples, weights and counters as the run made in
+    one go (gated, with a deterministic stand-in surrogate)."""
+    d = 3
+
+    def make():
+        gate = GatedLikelihood(CensoredSurrogate(), tau=0.05, first_train=600, retrain_every=500,
+                               window=2000, band=(2.0, 3.0), guard=0.5, stale_gap=40)
+        return NestedSampler(gauss_loglike, d, LO, HI, n_live=150, dlogz=0.05, batch=128, seed=9,
+                             gate=gate, audit_frac=0.1)
+
+    whole = make().run()
+    path = str(tmp_path / "ns.npz")
+    r, parts = make().run(time_limit=0.02, checkpoint=path), 1
+    while r is None:
+        r = make().run(time_limit=0.02, checkpoint=path, resume=path)
+        parts += 1
+    assert parts > 3
+    np.testing.assert_array_equal(r.samples, whole.samples)
+    np.testing.assert_array_equal(r.logw, whole.logw)
+    assert r.logz == whole.logz and r.iterations == whole.iterations
+    assert (r.n_exact, r.n_proposed, r.n_gate_rejected, r.n_audited, r.n_retrain) == \
+        (whole.n_exact, whole.n_proposed, whole.n_gate_rejected, whole.n_audited, whole.n_retrain)
