@@ -658,13 +658,15 @@ def main():
                     help="epochs of each warm retraining (0: as the first training)")
     ap.add_argument("--train-minibatch", type=int, default=512)
     ap.add_argument("--pool-factor", type=int, default=1)
-    ap.add_argument("--band-below", type=float, default=5.0,
+    ap.add_argument("--band-below", type=float, default=0.5,
                     help="gated: censor training targets this far below the threshold")
-    ap.add_argument("--band-above", type=float, default=0.0,
+    ap.add_argument("--band-above", type=float, default=1.0,
                     help="gated: ... and this far above it (0: no censoring; train near the threshold)")
-    ap.add_argument("--guard", type=float, default=1.0)
-    ap.add_argument("--whiten", action="store_true", help="gated: map inputs to the training data's box")
-    ap.add_argument("--cold", action="store_true", help="gated: every training from fresh weights")
+    ap.add_argument("--guard", type=float, default=0.25)
+    ap.add_argument("--no-whiten", dest="whiten", action="store_false",
+                    help="gated: keep the prior box as the inputs' scale (default: the training data's box)")
+    ap.add_argument("--no-cold", dest="cold", action="store_false",
+                    help="gated: retrain from the previous weights (default: from fresh weights)")
     ap.add_argument("--stale-gap", type=int, default=250)
     ap.add_argument("--phase", choices=["both", "plain", "gated", "compare"], default="both")
     ap.add_argument("--time-limit", type=float, default=None, help="gated workload, one phase: stop after this many s")

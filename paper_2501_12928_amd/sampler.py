@@ -244,7 +244,7 @@ class NestedSampler:
         th = np.concatenate(ths)
         self.stats["n_proposed"] += th.shape[0]
         return {"th": th, "L": np.full(th.shape[0], np.nan), "mean": np.concatenate(means),
-                "spread": np.concatenate(spreads), "pos": 0}
+                "spread": np.concatenate(spreads), "pos": 0, "band": self.gate.band_now()}
 
     def _confident_reject(self, pool, i, L_min):
         return (pool["mean"] is not None and pool["spread"][i] <= self.gate.tau
@@ -277,7 +277,7 @@ class NestedSampler:
                 # not below the threshold, so the point went to the exact call
                 conf = [j for j in idx if pool["spread"][j] <= self.gate.tau]
                 if conf:
-                    err = np.abs(pool["mean"][conf] - self.gate.censor(L[conf]))
+                    err = np.abs(pool["mean"][conf] - self.gate.censor(L[conf], pool.get("band")))
                     self.stats["n_conf_checked"] += len(conf)
                     self.stats["max_conf_err"] = max(self.stats["max_conf_err"], float(np.max(err)))
         return None
@@ -294,7 +294,9 @@ class NestedSampler:
         meta = dict(logz=float(st["logz"]), ln_x_prev=float(st["ln_x_prev"]), it=int(st["it"]),
                     elapsed=float(st["elapsed"]), t_train0=float(st["t_train0"]), stats=self.stats,
                     rng=self.rng.bit_generator.state, audit_rng=self.audit_rng.bit_generator.state,
-                    pool=None if pool is None else dict(pos=int(pool["pos"]), gated=pool["mean"] is not None))
+                    pool=None if pool is None else dict(pos=int(pool["pos"]), gated=pool["mean"] is not None,
+                                                        band=[float(v) for v in pool["band"]]
+                                                        if pool.get("band") is not None else None))
         if pool is not None:
             arrays["pool_th"] = pool["th"]
             arrays["pool_L"] = pool["L"]
@@ -320,7 +322,8 @@ class NestedSampler:
         if meta["pool"] is not None:
             pool = {"th": z["pool_th"], "L": z["pool_L"].copy(), "pos": meta["pool"]["pos"],
                     "mean": z["pool_mean"] if meta["pool"]["gated"] else None,
-                    "spread": z["pool_spread"] if meta["pool"]["gated"] else None}
+                    "spread": z["pool_spread"] if meta["pool"]["gated"] else None,
+                    "band": None if meta["pool"].get("band") is None else tuple(meta["pool"]["band"])}
         if self.gate is not None:
             self.gate.set_state({k[5:]: z[k] for k in z.files if k.startswith("gate_")}, meta["gate"])
         return dict(live=z["live"].copy(), live_L=z["live_L"].copy(), dead=list(z["dead"]),
@@ -509,9 +512,17 @@ class GatedLikelihood:
         self._L.append(np.asarray(L)[ok])
         self._count += int(ok.sum())
 
-    def censor(self, L):
-        """logL on the scale the network was trained on."""
-        return np.clip(L, self.floor, self.cap) if self.band is not None else L
+    def band_now(self):
+        """(floor, cap) of the network's current training targets."""
+        return (self.floor, self.cap)
+
+    def censor(self, L, band=None):
+        """logL on the scale the network was trained on (that of `band`,
+        the (floor, cap) in force when the predictions were made)."""
+        if self.band is None:
+            return L
+        lo, hi = band if band is not None else (self.floor, self.cap)
+        return np.clip(L, lo, hi)
 
     def reject_below(self, L_min):
         """Threshold under which a confident prediction is rejected."""
