@@ -482,6 +482,9 @@ eor_status eor_forward_model(int64_t n_freq, int64_t n_bl, int64_t n_pix, int64_
                              void *stream);
 
 /*
+ * DIAGNOSTIC, not part of the method: a measuring instrument for the
+ * benchmark's roofline report, kept in the library so that it runs with the
+ * same build and clock behaviour as the likelihood kernels.
  * Measured FP64 matrix peak (for reporting beside the specification peak):
  * back-to-back FP64 16x16x4 MFMAs on independent accumulators, two
  * workgroups of four waves per CU, `iters` rounds of eight per wave, timed on
