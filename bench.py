@@ -286,13 +286,13 @@ def gate_settings(args):
     band = None if args.band_above <= 0 else (args.band_below, args.band_above)
     kw = dict(tau=args.tau, first_train=args.first_train, retrain_every=args.retrain_every, window=args.window,
               margin=args.margin, train_kwargs={"cfg": cfg}, retrain_kwargs=None if rcfg is None else {"cfg": rcfg},
-              band=band, guard=args.guard, stale_gap=args.stale_gap, whiten=args.whiten, cold=args.cold, seed=11)
+              band=band, reach=args.reach, stale_gap=args.stale_gap, whiten=args.whiten, cold=args.cold, seed=11)
     text = (f"n_live={args.n_live}, gate tau={args.tau}, first training after {args.first_train} exact "
             f"evaluations ({args.train_epochs} epochs), retrain every {args.retrain_every} iterations on the last "
             f"{args.window} ({args.retrain_epochs or args.train_epochs} epochs, warm), "
             + (f"targets censored to [L_min - {args.band_below}, L_min + {args.band_above}] (band re-centred after "
-               f"the threshold climbs {args.band_above / 2}, at most every {args.stale_gap} iterations; guard "
-               f"{args.guard})" if band else f"within {args.margin} of the threshold")
+               f"the threshold climbs {args.band_above / 2}, at most every {args.stale_gap} iterations; rejected "
+               f"only within {args.reach} of the floor)" if band else f"within {args.margin} of the threshold")
             + (", inputs mapped to the training box" if args.whiten else "")
             + (", every training from fresh weights" if args.cold else "")
             + ", exact calls of 512 proposals the gate is unsure of")
@@ -310,7 +310,7 @@ def gated_pair(ctx, n_k, lo, hi, args, seed=7, progress=2000):
                           progress=progress).run()
     sur = eor.Surrogate(n_k, -1.0 if args.whiten else lo, 1.0 if args.whiten else hi, n_members=5, hidden=256, seed=1)
     gated = NestedSampler(loglike, n_k, lo, hi, n_live=args.n_live, dlogz=0.01, batch=512, seed=seed,
-                          gate=GatedLikelihood(sur, **kw), audit_frac=0.01, pool_factor=args.pool_factor,
+                          gate=GatedLikelihood(sur, **kw), audit_frac=args.audit_frac, pool_factor=args.pool_factor,
                           progress=progress).run()
     sur.close()
     cmp = compare_runs(plain, gated, args.n_live)
@@ -399,7 +399,7 @@ def bench_gated(args):
                             n_members=5, hidden=256, seed=1)
         gate = GatedLikelihood(sur, **kw)
     ns = NestedSampler(exact_gpu(ctx), inst.n_k, inst.lo, inst.hi, n_live=args.n_live, dlogz=0.01, batch=512,
-                       seed=7, gate=gate, audit_frac=0.01, pool_factor=args.pool_factor, progress=2000)
+                       seed=7, gate=gate, audit_frac=args.audit_frac, pool_factor=args.pool_factor, progress=2000)
     r = ns.run(time_limit=args.time_limit, checkpoint=args.checkpoint, resume=args.resume)
     if r is None:
         print(json.dumps({"phase": args.phase, "stopped": True, "checkpoint": args.checkpoint,
@@ -662,7 +662,10 @@ def main():
                     help="gated: censor training targets this far below the threshold")
     ap.add_argument("--band-above", type=float, default=1.0,
                     help="gated: ... and this far above it (0: no censoring; train near the threshold)")
-    ap.add_argument("--guard", type=float, default=0.25)
+    ap.add_argument("--reach", type=float, default=0.2,
+                    help="gated runs: reject a confident prediction only within this of the band's floor")
+    ap.add_argument("--audit-frac", type=float, default=0.01,
+                    help="gated runs: fraction of the gate's rejections evaluated anyway")
     ap.add_argument("--no-whiten", dest="whiten", action="store_false",
                     help="gated: keep the prior box as the inputs' scale (default: the training data's box)")
     ap.add_argument("--no-cold", dest="cold", action="store_false",

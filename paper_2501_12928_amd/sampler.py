@@ -20,7 +20,8 @@ With a gate (see GatedLikelihood), the surrogate's ensemble mean and
 spread are computed for a whole pool of proposals, and each proposal is
 judged when its turn comes, against the threshold of that moment: a
 proposal the surrogate is confident lies below it (spread <= tau and
-mean < L_min) is rejected without an exact evaluation; the uncertain ones
+mean below the gate's rejection line, at most L_min) is rejected without an
+exact evaluation; the uncertain ones
 are evaluated exactly, a batch of them at a time. Only exact values ever
 enter the live set, so every accepted point carries its exact FP64 logL. A
 small random fraction of the surrogate's rejections is evaluated anyway to
@@ -59,6 +60,10 @@ class Result:
     t_train_s: float
     n_conf_checked: int = 0    # confident predictions (spread <= tau) that went to an exact call anyway
     max_conf_err: float = 0.0  # ... their largest |mean - exact logL| (on the gate's censored scale)
+    # one row per audited rejection: exact logL, threshold in force, ensemble
+    # mean and spread, the band (floor, cap) the network was trained on, and
+    # the iteration (AUDIT_COLUMNS)
+    audit_log: np.ndarray | None = None
 
     def posterior_moments(self):
         w = np.exp(self.logw - self.logw.max())
@@ -107,12 +112,16 @@ class Result:
         return out
 
 
+AUDIT_COLUMNS = ("logl", "L_min", "mean", "spread", "floor", "cap", "iteration")
+
+
 def save_result(path, r: Result):
     """A Result as one .npz (arrays, and the scalars as JSON; no pickles)."""
     import json
-    meta = {f.name: getattr(r, f.name) for f in dataclasses.fields(r)
-            if f.name not in ("samples", "logl", "logw")}
-    np.savez(path, samples=r.samples, logl=r.logl, logw=r.logw,
+    arrays = ("samples", "logl", "logw", "audit_log")
+    meta = {f.name: getattr(r, f.name) for f in dataclasses.fields(r) if f.name not in arrays}
+    extra = {} if r.audit_log is None else {"audit_log": r.audit_log}
+    np.savez(path, samples=r.samples, logl=r.logl, logw=r.logw, **extra,
              meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
 
 
@@ -120,7 +129,8 @@ def load_result(path) -> Result:
     import json
     z = np.load(path, allow_pickle=False)
     meta = json.loads(z["meta"].tobytes().decode())
-    return Result(samples=z["samples"], logl=z["logl"], logw=z["logw"], **meta)
+    log = z["audit_log"] if "audit_log" in z.files else None
+    return Result(samples=z["samples"], logl=z["logl"], logw=z["logw"], audit_log=log, **meta)
 
 
 def _logsubexp(a, b):
@@ -151,7 +161,7 @@ class Ellipsoid:
 class NestedSampler:
     """loglike(theta [B, d] float64) -> logL [B]; gate (optional) is a
     GatedLikelihood-like object with predict(theta) -> (mean, spread) or
-    None, tau, trained, reject_below(L_min), censor(logL), observe(theta,
+    None, tau, trained, reject_below(L_min, band), band_now(), censor(logL, band), observe(theta,
     logL) and maybe_retrain(iteration, L_min).
 
     run() may stop at an iteration boundary once `time_limit` seconds have
@@ -229,7 +239,7 @@ class NestedSampler:
             self.stats["t_gate"] += time.perf_counter() - t0
             self.stats["n_screened"] += th.shape[0]
             self.stats["n_confident"] += int(np.count_nonzero(sp <= self.gate.tau))
-            u = ~((sp <= self.gate.tau) & (m < self.gate.reject_below(L_min)))
+            u = ~((sp <= self.gate.tau) & (m < self.gate.reject_below(L_min, self.gate.band_now())))
             c = np.cumsum(u)
             if unsure + int(c[-1]) >= self.batch:
                 cut = int(np.searchsorted(c, self.batch - unsure)) + 1
@@ -248,7 +258,7 @@ class NestedSampler:
 
     def _confident_reject(self, pool, i, L_min):
         return (pool["mean"] is not None and pool["spread"][i] <= self.gate.tau
-                and pool["mean"][i] < self.gate.reject_below(L_min))
+                and pool["mean"][i] < self.gate.reject_below(L_min, pool["band"]))
 
     def _next_valid(self, pool, L_min):
         """Index of the next proposal of the pool with exact logL > L_min,
@@ -266,7 +276,10 @@ class NestedSampler:
                 pool["pos"] += 1
                 self.stats["n_gate_rejected"] += 1
                 if self.audit_frac > 0 and self.audit_rng.uniform() < self.audit_frac:
-                    self._audits.append((th[i].copy(), L_min))  # judged in full batches at the end
+                    # judged in full batches at the end, with what the gate saw
+                    fl, cp = pool.get("band") or (np.nan, np.nan)
+                    self._audits.append((th[i].copy(), (L_min, float(pool["mean"][i]),
+                                                        float(pool["spread"][i]), fl, cp, self._it)))
                 continue
             # evaluate exactly, in one call, the rest of the pool that the gate is unsure of
             idx = [j for j in range(i, th.shape[0])
@@ -290,7 +303,7 @@ class NestedSampler:
         arrays = dict(live=st["live"], live_L=st["live_L"], dead=np.array(st["dead"]).reshape(-1, self.d),
                       dead_L=np.array(st["dead_L"]), dead_lnw=np.array(st["dead_lnw"]),
                       audit_th=np.array([a for a, _ in self._audits]).reshape(-1, self.d),
-                      audit_L=np.array([b for _, b in self._audits]))
+                      audit_info=np.array([b for _, b in self._audits], dtype=np.float64).reshape(-1, 6))
         meta = dict(logz=float(st["logz"]), ln_x_prev=float(st["ln_x_prev"]), it=int(st["it"]),
                     elapsed=float(st["elapsed"]), t_train0=float(st["t_train0"]), stats=self.stats,
                     rng=self.rng.bit_generator.state, audit_rng=self.audit_rng.bit_generator.state,
@@ -317,7 +330,12 @@ class NestedSampler:
         self.stats = meta["stats"]
         self.rng.bit_generator.state = meta["rng"]
         self.audit_rng.bit_generator.state = meta["audit_rng"]
-        self._audits = [(z["audit_th"][k].copy(), float(z["audit_L"][k])) for k in range(z["audit_L"].shape[0])]
+        if "audit_info" in z.files:
+            info = z["audit_info"]
+        else:   # files written before the gate's view was kept: the threshold only
+            info = np.full((z["audit_L"].shape[0], 6), np.nan)
+            info[:, 0] = z["audit_L"]
+        self._audits = [(z["audit_th"][k].copy(), tuple(float(v) for v in info[k])) for k in range(info.shape[0])]
         pool = None
         if meta["pool"] is not None:
             pool = {"th": z["pool_th"], "L": z["pool_L"].copy(), "pos": meta["pool"]["pos"],
@@ -356,7 +374,7 @@ class NestedSampler:
             t_train0 = self.gate.train_seconds if self.gate is not None else 0.0
             if self.gate is not None:
                 self.gate.maybe_retrain(it, float(np.min(live_L)))
-        it_call = it
+        it_call = self._it = it
         while it < self.max_iter:
             if time_limit is not None and it > it_call and time.perf_counter() - t_call > time_limit:
                 self._save(checkpoint, dict(live=live, live_L=live_L, dead=dead, dead_L=dead_L,
@@ -373,6 +391,7 @@ class NestedSampler:
             dead_lnw.append(ln_w)
             ln_x_prev = ln_x
             it += 1
+            self._it = it
             # replacement: the next pooled proposal above the threshold
             j = None if pool is None else self._next_valid(pool, L_min)
             while j is None:
@@ -393,11 +412,14 @@ class NestedSampler:
                 break
         # audits of gate rejections: exact logL against the threshold in force
         # when each was rejected (they change nothing in the run)
+        log = [np.zeros((0, len(AUDIT_COLUMNS)))]
         for a in range(0, len(self._audits), self.batch):
             chunk = self._audits[a:a + self.batch]
             La = self._exact(np.stack([t for t, _ in chunk]))
+            info = np.array([b for _, b in chunk], dtype=np.float64)
             self.stats["n_audited"] += len(chunk)
-            self.stats["n_false_reject"] += int(sum(v > lm for v, (_, lm) in zip(La, chunk)))
+            self.stats["n_false_reject"] += int(np.count_nonzero(La > info[:, 0]))
+            log.append(np.column_stack([La, info]))
         # the final live points share the remaining prior volume
         ln_wl = live_L + ln_x_prev - math.log(n)
         logz_final = np.logaddexp(logz, np.logaddexp.reduce(ln_wl))
@@ -416,7 +438,8 @@ class NestedSampler:
                       n_retrain=self.gate.n_train if self.gate is not None else 0,
                       wall_s=time.perf_counter() - t_start, t_exact_s=st["t_exact"], t_gate_s=st["t_gate"],
                       t_train_s=(self.gate.train_seconds - t_train0) if self.gate is not None else 0.0,
-                      n_conf_checked=st["n_conf_checked"], max_conf_err=st["max_conf_err"])
+                      n_conf_checked=st["n_conf_checked"], max_conf_err=st["max_conf_err"],
+                      audit_log=np.concatenate(log))
 
 
 class GatedLikelihood:
@@ -440,18 +463,28 @@ class GatedLikelihood:
       predicts the floor, which is below every later threshold. The flat
       parts are easy to fit, so the ensemble agrees there (small spread) even
       early in the run, when logL spans thousands of units over the live
-      points and its uncensored fit could never reach a spread of tau. Above
-      the band the network predicts the band's top, so a rejection is
-      trusted only below min(L_min, top - guard), a stricter rule than the
-      plain one; the band is re-centred by retraining once L_min has climbed
-      half its upper width (at most once per `stale_gap` iterations).
+      points and its uncensored fit could never reach a spread of tau. The
+      band is re-centred by retraining once L_min has climbed half its upper
+      width (at most once per `stale_gap` iterations), so early in the run,
+      when the threshold climbs fast, it lies far above the band most of the
+      time and every valid proposal's target is the band's top.
+
+      A rejection is trusted only where the network places the proposal at
+      the floor: mean < min(L_min, floor + reach). Predictions between the
+      floor and the top are not trusted even below L_min: with a stale band
+      they are where the network's gross errors land (valid points many
+      units above the threshold read in the middle of the band), and such
+      losses are not harmless: they fall on the lower part of the valid
+      region, so the replacements drift inward, the threshold climbs too
+      fast and ln Z comes out high. A point at the floor lies at least
+      `below` - `reach` under every later threshold.
 
     surrogate: an object with train(theta, logL, ...) and gate(theta, L_min,
     tau) -> (mean, spread, decision) (paper_2501_12928_amd.Surrogate, or any
     stand-in with that interface)."""
 
     def __init__(self, surrogate, tau=0.05, first_train=100_000, retrain_every=0, window=100_000,
-                 margin=np.inf, train_kwargs=None, retrain_kwargs=None, band=None, guard=1.0, stale_gap=250,
+                 margin=np.inf, train_kwargs=None, retrain_kwargs=None, band=None, reach=0.2, stale_gap=250,
                  whiten=False, cold=False, seed=0):
         self.s = surrogate
         self.tau = float(tau)
@@ -471,7 +504,7 @@ class GatedLikelihood:
         self.train_seconds = 0.0
         self._last_iter = 0
         self.band = None if band is None else (float(band[0]), float(band[1]))
-        self.guard = float(guard)
+        self.reach = float(reach)
         self.stale_gap = int(stale_gap)
         self.L_ref = -np.inf   # threshold at the last training
         self.floor = -np.inf   # band the network was trained on
@@ -524,24 +557,33 @@ class GatedLikelihood:
         lo, hi = band if band is not None else (self.floor, self.cap)
         return np.clip(L, lo, hi)
 
-    def reject_below(self, L_min):
-        """Threshold under which a confident prediction is rejected."""
-        return L_min if self.band is None else min(L_min, self.cap - self.guard)
+    def reject_below(self, L_min, band=None):
+        """Line under which a confident prediction is rejected, for
+        predictions made on `band` (the (floor, cap) in force when they were
+        made; the current one by default): a pool screened before a retraining
+        keeps the old network's predictions, on the old band's scale."""
+        if self.band is None:
+            return L_min
+        floor = band[0] if band is not None else self.floor
+        return min(L_min, floor + self.reach)
 
     def _train(self, L_min):
         th = np.concatenate(self._th)
         L = np.concatenate(self._L)
-        keep = max(self.window * 4, 1)
+        keep = max(self.window * 4, self.first_train, 1)
         th, L = th[-keep:], L[-keep:]           # bounded history
         self._th, self._L = [th], [L]
+        # the first training takes every evaluation made so far (first_train
+        # of them), later ones the last `window`
+        use = self.window if self.trained else max(self.window, self.first_train)
         if self.band is None:
             near = L >= L_min - self.margin
             if np.count_nonzero(near) >= 256:
                 th, L = th[near], L[near]
-            th, y = th[-self.window:], L[-self.window:]
+            th, y = th[-use:], L[-use:]
         else:
             self.floor, self.cap = L_min - self.band[0], L_min + self.band[1]
-            th, y = th[-self.window:], np.clip(L[-self.window:], self.floor, self.cap)
+            th, y = th[-use:], np.clip(L[-use:], self.floor, self.cap)
         t0 = time.perf_counter()
         if self.whiten:
             lo, hi = th.min(axis=0), th.max(axis=0)
@@ -625,7 +667,7 @@ def exact_gpu(ctx):
 
 def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0.05, first_train=100_000,
                         retrain_every=0, window=100_000, margin=np.inf, train_cfg=None, batch=512, dlogz=0.01,
-                        audit_frac=0.01, pool_factor=1, progress=0, retrain_cfg=None, band=None, guard=1.0,
+                        audit_frac=0.01, pool_factor=1, progress=0, retrain_cfg=None, band=None, reach=0.2,
                         stale_gap=250):
     """The same nested-sampling run without and with the surrogate gate
     (same seed), and the comparison: evidence, per-bin posterior mean and
@@ -637,7 +679,7 @@ def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0
                            window=window, margin=margin,
                            train_kwargs={"cfg": train_cfg} if train_cfg is not None else {},
                            retrain_kwargs={"cfg": retrain_cfg} if retrain_cfg is not None else None,
-                           band=band, guard=guard, stale_gap=stale_gap)
+                           band=band, reach=reach, stale_gap=stale_gap)
     gated = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
                           gate=gate, audit_frac=audit_frac, pool_factor=pool_factor, progress=progress).run()
     return plain, gated, compare_runs(plain, gated, n_live)
