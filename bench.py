@@ -289,7 +289,7 @@ def gate_settings(args):
               band=band, reach=args.reach, stale_gap=args.stale_gap, whiten=args.whiten, cold=args.cold, seed=11)
     text = (f"n_live={args.n_live}, gate tau={args.tau}, first training after {args.first_train} exact "
             f"evaluations ({args.train_epochs} epochs), retrain every {args.retrain_every} iterations on the last "
-            f"{args.window} ({args.retrain_epochs or args.train_epochs} epochs, warm), "
+            f"{args.window} ({args.retrain_epochs or args.train_epochs} epochs{'' if args.cold else ', warm'}), "
             + (f"targets censored to [L_min - {args.band_below}, L_min + {args.band_above}] (band re-centred after "
                f"the threshold climbs {args.band_above / 2}, at most every {args.stale_gap} iterations; rejected "
                f"only within {args.reach} of the floor)" if band else f"within {args.margin} of the threshold")
