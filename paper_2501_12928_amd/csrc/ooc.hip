@@ -470,8 +470,11 @@ int64_t ntiles(int64_t N) { return N * (N + 1) / 2; }
 
 // Device bytes: shared dbar, bin map, fixed variances and scales; per lane
 // Linv, w and y, the state and theta and result slots, then the lane's
-// share of what is left in tiles, half of it for the pass (whole tile
-// columns) and the rest for the window of earlier columns.
+// share of what is left in tiles, in whole full-height tile columns. The
+// bytes over the host link depend only on the pass width (the rows of every
+// earlier column below a pass cross once per pass); the window of earlier
+// columns only sets how many of them one window kernel sums. So the window
+// keeps min(4, half) of the columns and the pass takes the rest.
 eor_status ooc_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes, OocPlan &p) {
     p.N = (n + OT - 1) / OT;
     p.n_pad = p.N * OT;
@@ -505,7 +508,8 @@ eor_status ooc_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes, 
     const int64_t avail = avail_of(L);
     if (avail < 2 * p.N) return fail_status(EOR_ERR_OOM, "eor_loglike_host: device_bytes below two columns of tiles per lane");
     p.lanes = L;
-    p.J = std::max<int64_t>(1, std::min<int64_t>(p.N, (avail / 2) / p.N));
+    const int64_t cols = avail / p.N;  // >= 2
+    p.J = std::min<int64_t>(p.N, cols - std::min<int64_t>(4, cols / 2));
     p.capC = p.J * p.N;
     p.cap = avail - p.capC;  // >= N
     int64_t t = 2 * ntiles(p.N);

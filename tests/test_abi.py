@@ -73,23 +73,24 @@ def test_argument_errors_without_gpu():
 
 def test_out_of_core_plan():
     """The out-of-core schedule, computed on the host without a device call:
-    pass width from the device budget per lane (half of a lane's tiles, in
-    whole tile columns), the automatic lane count, and the host <-> device
-    bytes per theta (A and L once each, plus every earlier tile column's rows
-    below a pass, once per pass)."""
+    pass width from the device budget per lane (a lane's tiles in whole
+    full-height tile columns, less min(4, half) of them for the window of
+    earlier columns), the automatic lane count, and the host <-> device bytes
+    per theta (A and L once each, plus every earlier tile column's rows below
+    a pass, once per pass)."""
     import paper_2501_12928_amd as eor
     tile = 64 * 64 * 16
     N = 64
-    # one lane at 256 MiB, n = 4096: 4091 tiles after the vectors -> 31 columns per pass
+    # one lane at 256 MiB, n = 4096: 4091 tiles after the vectors = 63 columns -> 59 per pass
     p = eor.loglike_host_plan(4096, 12, 256 << 20, lanes=1)
-    assert p["lanes"] == 1 and p["cols_per_pass"] == 31
-    assert p["window_tiles"] >= N
-    moved = 2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 31))
+    assert p["lanes"] == 1 and p["cols_per_pass"] == 59
+    assert p["window_tiles"] == 4091 - 59 * N
+    moved = 2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 59))
     assert p["link_bytes"] == moved * tile
-    # automatic: four lanes would leave 1020 tiles each (< 2 x 8 x 64), two leave 2044 -> 15 columns
+    # automatic: four lanes would leave 1020 tiles each (< 2 x 8 x 64), two leave 2044 = 31 columns -> 27
     p = eor.loglike_host_plan(4096, 12, 256 << 20)
-    assert p["lanes"] == 2 and p["cols_per_pass"] == 15
-    assert p["link_bytes"] == (2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 15))) * tile
+    assert p["lanes"] == 2 and p["cols_per_pass"] == 27 and p["window_tiles"] == 2044 - 27 * N
+    assert p["link_bytes"] == (2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 27))) * tile
     # the smallest budget of the GPU tests (n = 333: 6 tile rows, 14 tiles): one lane, one column per pass
     p = eor.loglike_host_plan(333, 4, 14 * tile)
     assert p == {"lanes": 1, "cols_per_pass": 1, "window_tiles": 6,

@@ -84,6 +84,28 @@ def test_ooc_two_lanes_several_passes(orc):
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
 
 
+def test_ooc_wide_pass_narrow_window(orc):
+    """The pass takes all but four columns of the window (n = 1200: 19 tile
+    rows, 8 columns per pass, 77 tiles of window): the second pass sums its
+    8 earlier columns in two window launches (7 + 1). 6 theta against the
+    oracle."""
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=75, m=2500, n=1200, n_k=5, n_theta=6)
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    ref, rinfo = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, inst.theta)
+    assert np.all(rinfo == 0)
+    N = 19
+    budget = (12 * N + 2) * TILE_BYTES + 4 * N * 64 * 16 + 8192 + 12 * inst.n
+    plan = eor.loglike_host_plan(inst.n, inst.n_k, budget, 1)
+    assert plan["cols_per_pass"] == 8 and plan["window_tiles"] == 77
+    print(f"gpu: out-of-core wide pass n=1200 budget={budget}", flush=True)
+    got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
+                                 inst.theta, budget, lanes=1)
+    assert np.all(info == 0)
+    assert np.all(np.abs(got - ref) <= tol(ref))
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
+
+
 def test_ooc_full_size_against_stored_oracle_values():
     """20000 x 4096, 12 bins: the GPU precompute, A exported to host memory,
     then the out-of-core factorisation through a 256 MiB device window, for

@@ -22,7 +22,8 @@ def _schedule(n, avail, bs=4, seed=0):
         for i in range(k, N):
             Ah[col_off(k) + i - k] = S[i * bs:(i + 1) * bs, k * bs:(k + 1) * bs].copy()
     Lh = [None] * ntile
-    J = max(1, min(N, (avail // 2) // N))
+    cols = avail // N                      # full-height tile columns that fit (>= 2)
+    J = min(N, cols - min(4, cols // 2))   # the window keeps min(4, half) of them
     capC, cap = J * N, avail - J * N
     assert cap >= N
     for j0 in range(0, N, J):
@@ -76,7 +77,8 @@ def _schedule(n, avail, bs=4, seed=0):
     return np.tril(L), np.linalg.cholesky(S)
 
 
-@pytest.mark.parametrize("n,avail", [(40, 20), (40, 25), (40, 60), (37, 100), (8, 4), (4, 2), (64, 32)])
+@pytest.mark.parametrize("n,avail", [(40, 20), (40, 25), (40, 60), (37, 100), (8, 4), (4, 2), (64, 32), (40, 75),
+                                     (64, 150), (61, 260)])
 def test_schedule_reproduces_cholesky(n, avail):
     L, ref = _schedule(n, avail)
     assert np.max(np.abs(L - ref)) <= 1e-13 * np.max(np.abs(ref))
