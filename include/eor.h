@@ -418,8 +418,8 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
  *   device_bytes: the device memory the call may use, split evenly between
  *            the lanes; each lane needs one column of tiles twice over (about
  *            2 ceil(n/64) x 64 KiB) plus O(n)
- *   lanes    1..4, or 0: as many (4, 2 or 1) as leave every lane at least
- *            min(ceil(n/64), 8) tile columns per pass and keep the pinned
+ *   lanes    1..4, or 0: as many (4, 2 or 1) as leave every lane room for
+ *            2 min(ceil(n/64), 8) full-height tile columns and keep the pinned
  *            host buffers (lanes + 1 copies of the packed lower triangle)
  *            within half of the host's physical memory
  * The schedule (lanes, pass width) follows from n, n_k, device_bytes and

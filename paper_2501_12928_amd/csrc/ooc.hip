@@ -488,9 +488,9 @@ eor_status ooc_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes, 
     };
     int L = lanes;
     if (lanes == 0) {
-        // as many lanes (up to four) as keep at least min(N, 8) tile columns
-        // per pass each, and their pinned factors (plus the packed A) within
-        // half of the host's physical memory
+        // as many lanes (up to four) as leave each room for 2 min(N, 8)
+        // full-height tile columns, and their pinned factors (plus the packed
+        // A) within half of the host's physical memory
         L = 1;
         const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
         const double host = pages > 0 && page > 0 ? (double)pages * (double)page : 0.0;
