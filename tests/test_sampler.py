@@ -250,3 +250,27 @@ def test_floor_rule_never_trusts_mid_band_predictions():
     L, L_min, mean, spread, floor, cap, it = safe.audit_log.T
     assert np.all(mean < np.minimum(L_min, floor + 0.2)) and np.all(spread <= 0.05)
     assert np.all(L <= L_min) and np.all(np.diff(it) >= 0)
+
+
+def test_result_file_round_trip(tmp_path):
+    """save_result / load_result keep every field, the audit log included
+    (arrays and JSON scalars, no pickles), and files without an audit log
+    load with audit_log None."""
+    from paper_2501_12928_amd.sampler import AUDIT_COLUMNS, load_result, save_result
+    d = 3
+    gate = GatedLikelihood(CensoredSurrogate(), tau=0.05, first_train=600, retrain_every=500,
+                           window=2000, band=(2.0, 3.0), reach=1.5, stale_gap=40)
+    r = NestedSampler(gauss_loglike, d, LO, HI, n_live=150, dlogz=0.05, batch=128, seed=4,
+                      gate=gate, audit_frac=0.2).run()
+    assert r.audit_log.shape == (r.n_audited, len(AUDIT_COLUMNS)) and r.n_audited > 0
+    path = str(tmp_path / "r.npz")
+    save_result(path, r)
+    back = load_result(path)
+    for f in ("samples", "logl", "logw", "audit_log"):
+        np.testing.assert_array_equal(getattr(back, f), getattr(r, f))
+    assert (back.logz, back.iterations, back.n_exact, back.n_audited) == (r.logz, r.iterations, r.n_exact,
+                                                                          r.n_audited)
+    plain = NestedSampler(gauss_loglike, d, LO, HI, n_live=100, dlogz=0.05, batch=128, seed=4).run()
+    plain.audit_log = None
+    save_result(path, plain)
+    assert load_result(path).audit_log is None
