@@ -668,10 +668,11 @@ def exact_gpu(ctx):
 def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0.05, first_train=100_000,
                         retrain_every=0, window=100_000, margin=np.inf, train_cfg=None, batch=512, dlogz=0.01,
                         audit_frac=0.01, pool_factor=1, progress=0, retrain_cfg=None, band=None, reach=0.2,
-                        stale_gap=250):
+                        stale_gap=250, whiten=False, cold=False):
     """The same nested-sampling run without and with the surrogate gate
     (same seed), and the comparison: evidence, per-bin posterior mean and
-    standard deviation, exact calls avoided and wall-clock speedup."""
+    standard deviation, exact calls avoided and wall-clock speedup. With
+    whiten, the surrogate's own input box must be [-1, 1]."""
     loglike = exact_gpu(ctx)
     plain = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
                           progress=progress).run()
@@ -679,7 +680,7 @@ def run_plain_and_gated(ctx, n_dim, lo, hi, surrogate, n_live=500, seed=0, tau=0
                            window=window, margin=margin,
                            train_kwargs={"cfg": train_cfg} if train_cfg is not None else {},
                            retrain_kwargs={"cfg": retrain_cfg} if retrain_cfg is not None else None,
-                           band=band, reach=reach, stale_gap=stale_gap)
+                           band=band, reach=reach, stale_gap=stale_gap, whiten=whiten, cold=cold, seed=seed)
     gated = NestedSampler(loglike, n_dim, lo, hi, n_live=n_live, dlogz=dlogz, batch=batch, seed=seed,
                           gate=gate, audit_frac=audit_frac, pool_factor=pool_factor, progress=progress).run()
     return plain, gated, compare_runs(plain, gated, n_live)
