@@ -175,12 +175,15 @@ def small(seed: int, m: int, n: int, n_k: int, n_eor: int | None = None,
 
 
 def stress_T(rng: np.random.Generator, m: int, n: int, decades: float = 4.0) -> np.ndarray:
-    """Ill-conditioned instrument matrix T = U diag(s) V^H with singular
-    values log-spaced over `decades` decades (orthonormal U, unitary V)."""
-    U, _ = np.linalg.qr(_cn(rng, (m, n), 1.0))
-    V, _ = np.linalg.qr(_cn(rng, (n, n), 1.0))
+    """Ill-conditioned instrument matrix T = G diag(s): the columns of a
+    complex Gaussian G (entries CN(0, 1/m), so every column has norm about 1
+    and G's own condition number is about (1 + sqrt(n/m)) / (1 - sqrt(n/m)))
+    scaled by s log-spaced over `decades` decades, so that T's singular
+    values spread over about as many. Elementwise arithmetic only: the same
+    bits on any host (a QR or a matrix product would round differently
+    with the host's BLAS)."""
     s = np.logspace(0.0, -decades, n)
-    return np.ascontiguousarray((U * s[None, :]) @ V.conj().T)
+    return np.ascontiguousarray(_cn(rng, (m, n), 1.0 / m) * s[None, :])
 
 
 def stress(seed: int, m: int, n: int, n_k: int, n_eor: int | None = None, n_theta: int = 8,

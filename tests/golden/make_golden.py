@@ -7,6 +7,7 @@ only. Run from the repository root:
     python tests/golden/make_golden.py c1 [n_sample]
     python tests/golden/make_golden.py c3 [n_sample]
     python tests/golden/make_golden.py c2
+    python tests/golden/make_golden.py stress [n_sample]
 
 For the 20000 x 4096 workload the fixture also holds theta chosen outside the
 batch (`extra_theta`): the corners and edges of the prior box [-1, 3]^12,
@@ -113,12 +114,36 @@ def group_sampled(pick=(11, 17, 9), n_theta=2):
         json.dump(out, f, indent=1)
 
 
+def stress_sampled(n_sample=8):
+    """Oracle logL at an evenly spaced sample of the theta batch of each
+    full-size ill-conditioned instance (synth.STRESS: T with singular values
+    over four decades, with the usual foreground share and with a wide-field
+    foreground model)."""
+    import oracle
+    orc = oracle.get()
+    out = {"cases": {}}
+    for name in sorted(synth.STRESS):
+        inst = synth.gen_stress(name)
+        B = inst.theta.shape[0]
+        idx = np.unique(np.linspace(0, B - 1, n_sample).round().astype(int))
+        t0 = time.time()
+        logL, info = orc.loglike_instance(inst, theta=inst.theta[idx])
+        out["cases"][name] = {"digest": inst.digest(), "m": inst.m, "n": inst.n, "n_k": inst.n_k, "B": B,
+                              "index": idx.tolist(), "logL": logL.tolist(), "info": info.tolist(),
+                              "oracle_seconds": time.time() - t0}
+        print(name, time.time() - t0, flush=True)
+    with open(os.path.join(HERE, "stress_oracle_sample.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1]
     if what == "digests":
         digests()
     elif what == "c2":
         group_sampled()
+    elif what == "stress":
+        stress_sampled(int(sys.argv[2]) if len(sys.argv) > 2 else 8)
     else:
         cid = int(what[1:])
         sampled(cid, int(sys.argv[2]) if len(sys.argv) > 2 else 8, with_extra=(cid == 3))

@@ -174,3 +174,30 @@ def test_stress_reduced_precision_reports_cleanly(orc, case, prec):
     if ok.any():
         print(f"  {case} {prec}: {int((~ok).sum())} of {info.size} failed; max |dlogL| "
               f"{np.max(np.abs(got[ok] - ref[ok])):.3g}", flush=True)
+
+
+@pytest.mark.parametrize("case", sorted(synth.STRESS))
+def test_stress_full_size_sampled(case):
+    """The ill-conditioned instances at full size (8000 x 2048, 8 bins,
+    B = 256 in one call, singular values of T over four decades; wide-field:
+    256 EoR against 1792 foreground coefficients), FP64: 8 theta of the batch
+    against oracle values stored by tests/golden/make_golden.py, failure codes
+    included, and every other theta finite or reported."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "stress_oracle_sample.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = json.load(open(path))["cases"][case]
+    inst = synth.gen_stress(case)
+    assert inst.digest() == g["digest"], "synthetic inputs differ from the ones the oracle saw"
+    print(f"gpu: stress {case} full size m={inst.m} n={inst.n} B={inst.theta.shape[0]}", flush=True)
+    got, info = run_instance(inst)
+    idx = np.array(g["index"])
+    ref, rinfo = np.array(g["logL"]), np.array(g["info"])
+    np.testing.assert_array_equal(info[idx], rinfo)
+    ok = rinfo == 0
+    assert ok.any()
+    assert np.all(np.abs(got[idx][ok] - ref[ok]) <= tol(ref[ok])), np.max(np.abs(got[idx][ok] - ref[ok]))
+    assert np.all(got[idx][~ok] == -np.inf)
+    assert np.all(np.isfinite(got[info == 0])) and np.all(got[info != 0] == -np.inf)
