@@ -219,3 +219,16 @@ def test_planted_mistake_fails_a_pin(mutant, tmp_path):
     ref = np.array([_pins.brute_loglike(inst.T, inst.noise_var, inst.d, th, inst.bin_of,
                                         inst.fixed_var) for th in inst.theta])
     assert np.max(_pins.rel_err(logL, ref)) > 1e-6
+
+
+def test_stress_generator_is_host_independent_and_ill_conditioned():
+    """The ill-conditioned instances are built with elementwise arithmetic
+    only, so the stored full-size oracle values stay valid: their digests
+    match the generator here. T's singular values spread over about the four
+    decades of its column scales."""
+    import json
+    g = json.load(open(_golden("stress_oracle_sample.json")))["cases"]
+    for name in sorted(synth.STRESS):
+        assert synth.gen_stress(name).digest() == g[name]["digest"], name
+    sv = np.linalg.svd(synth.stress(35, m=700, n=300, n_k=3).T, compute_uv=False)
+    assert 3e3 < sv[0] / sv[-1] < 1e5
