@@ -418,7 +418,7 @@ eor_status eor_compact_rows(int64_t n, int32_t n_cols, const int32_t *keep, cons
  *   device_bytes: the device memory the call may use, split evenly between
  *            the lanes; each lane needs one column of tiles twice over (about
  *            2 ceil(n/64) x 64 KiB) plus O(n)
- *   lanes    1..4, or 0: as many (4, 2 or 1) as leave every lane room for
+ *   lanes    1..4, or 0: as many (at most 4) as leave every lane room for
  *            2 min(ceil(n/64), 8) full-height tile columns and keep the pinned
  *            host buffers (lanes + 1 copies of the packed lower triangle)
  *            within half of the host's physical memory
@@ -444,9 +444,10 @@ eor_status eor_loglike_host(int device, int64_t n, const double *A, int64_t ldA,
  * The schedule eor_loglike_host follows for these arguments, without running
  * it (host only, no device call): lanes_out, the tile columns per pass
  * (cols_per_pass), the tiles of a lane's window of earlier columns
- * (window_tiles) and the host <-> device bytes per theta (link_bytes: A and
- * L once each, and the rows of every earlier tile column below a pass once
- * per pass). Any output pointer may be NULL. Errors as eor_loglike_host's
+ * (window_tiles) and the host <-> device bytes per theta (link_bytes: A
+ * once, the rows of every earlier tile column below a pass once per pass, and
+ * the part of each pass's columns that later passes read, written back once).
+ * Any output pointer may be NULL. Errors as eor_loglike_host's
  * for the same arguments (EOR_ERR_ARG, EOR_ERR_OOM).
  */
 eor_status eor_loglike_host_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes,

@@ -494,7 +494,7 @@ eor_status ooc_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes, 
         L = 1;
         const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
         const double host = pages > 0 && page > 0 ? (double)pages * (double)page : 0.0;
-        for (int cand = MAX_LANES; cand > 1; cand /= 2) {
+        for (int cand = MAX_LANES; cand > 1; --cand) {
             const int64_t av = avail_of(cand);
             const bool fits_host = (double)(cand + 1) * (double)ntiles(p.N) * (double)TILE_B <= 0.5 * host;
             if (av >= 2 * std::min<int64_t>(p.N, 8) * p.N && fits_host) {
@@ -512,8 +512,13 @@ eor_status ooc_plan(int64_t n, int32_t n_k, size_t device_bytes, int32_t lanes, 
     p.J = std::min<int64_t>(p.N, cols - std::min<int64_t>(4, cols / 2));
     p.capC = p.J * p.N;
     p.cap = avail - p.capC;  // >= N
-    int64_t t = 2 * ntiles(p.N);
-    for (int64_t j0 = 0; j0 < p.N; j0 += p.J) t += j0 * (p.N - j0);
+    // A once; every earlier column's rows below each pass; and, written back,
+    // the rows of a pass's columns that a later pass reads (rows j1 .. N-1)
+    int64_t t = ntiles(p.N);
+    for (int64_t j0 = 0; j0 < p.N; j0 += p.J) {
+        const int64_t j1 = std::min<int64_t>(p.N, j0 + p.J);
+        t += j0 * (p.N - j0) + (j1 - j0) * (p.N - j1);
+    }
     p.link_bytes = t * (int64_t)TILE_B;
     return EOR_OK;
 }
@@ -720,8 +725,13 @@ extern "C" eor_status eor_loglike_host(int device, int64_t n, const double *A, i
                     hipLaunchKernelGGL(ooc_pass_kernel, dim3((unsigned)(col_off(j1) - col_off(j + 1))), dim3(256), 0,
                                        s, L.C.p, j, j0, j1, N, L.st.p);
             }
-            // tile columns j0 .. j1-1 of L to the host factor: one contiguous block
-            e = hipMemcpyAsync(L.Lh + col_off(j0) * OT2, L.C.p, (size_t)nt * TILE_B, hipMemcpyDeviceToHost, s);
+            // to the host factor, what later passes read of tile columns j0 .. j1-1:
+            // rows j1 .. N-1 of each (none after the last pass; the rows above j1
+            // were only ever needed inside this pass)
+            for (int64_t j = j0; j < j1 && j1 < N && e == hipSuccess; ++j)
+                e = hipMemcpyAsync(L.Lh + (col_off(j) + (j1 - j)) * OT2,
+                                   L.C.p + (col_off(j) - col_off(j0) + (j1 - j)) * OT2, (size_t)(N - j1) * TILE_B,
+                                   hipMemcpyDeviceToHost, s);
         }
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(ooc_finish_kernel, dim3(1), dim3(1), 0, s, L.st.p, K0, c, L.out.p, L.info.p);

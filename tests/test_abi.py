@@ -71,13 +71,22 @@ def test_argument_errors_without_gpu():
     assert L.eor_loglike_host(*args(4, bins, fv, 1 << 30, -1)) == eor.EOR_ERR_ARG
 
 
+def _moved(N, J):
+    """Tiles over the host link per theta for N tile rows in passes of J."""
+    t = N * (N + 1) // 2
+    for j0 in range(0, N, J):
+        j1 = min(N, j0 + J)
+        t += j0 * (N - j0) + (j1 - j0) * (N - j1)
+    return t
+
+
 def test_out_of_core_plan():
     """The out-of-core schedule, computed on the host without a device call:
     pass width from the device budget per lane (a lane's tiles in whole
     full-height tile columns, less min(4, half) of them for the window of
     earlier columns), the automatic lane count, and the host <-> device bytes
-    per theta (A and L once each, plus every earlier tile column's rows below
-    a pass, once per pass)."""
+    per theta (A once, every earlier tile column's rows below a pass once per
+    pass, and rows j1 .. N-1 of each pass's columns written back)."""
     import paper_2501_12928_amd as eor
     tile = 64 * 64 * 16
     N = 64
@@ -85,19 +94,24 @@ def test_out_of_core_plan():
     p = eor.loglike_host_plan(4096, 12, 256 << 20, lanes=1)
     assert p["lanes"] == 1 and p["cols_per_pass"] == 59
     assert p["window_tiles"] == 4091 - 59 * N
-    moved = 2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 59))
-    assert p["link_bytes"] == moved * tile
-    # automatic: four lanes would leave 1020 tiles each (< 2 x 8 x 64), two leave 2044 = 31 columns -> 27
+    assert p["link_bytes"] == _moved(N, 59) * tile
+    # automatic: four lanes would leave 1020 tiles each (< 2 x 8 x 64), three leave 1361 = 21 columns -> 17
     p = eor.loglike_host_plan(4096, 12, 256 << 20)
+    assert p["lanes"] == 3 and p["cols_per_pass"] == 17 and p["window_tiles"] == 1361 - 17 * N
+    assert p["link_bytes"] == _moved(N, 17) * tile
+    # two lanes leave 2044 = 31 columns -> 27
+    p = eor.loglike_host_plan(4096, 12, 256 << 20, lanes=2)
     assert p["lanes"] == 2 and p["cols_per_pass"] == 27 and p["window_tiles"] == 2044 - 27 * N
-    assert p["link_bytes"] == (2 * (N * (N + 1) // 2) + sum(j0 * (N - j0) for j0 in range(0, N, 27))) * tile
+    assert p["link_bytes"] == _moved(N, 27) * tile
+    # 64 tile rows, passes of 27: A 2080 tiles, earlier rows 27 x 37 + 54 x 10, written back 27 x 37 + 27 x 10
+    assert _moved(N, 27) == 2080 + 999 + 540 + 999 + 270
     # the smallest budget of the GPU tests (n = 333: 6 tile rows, 14 tiles): one lane, one column per pass
     p = eor.loglike_host_plan(333, 4, 14 * tile)
     assert p == {"lanes": 1, "cols_per_pass": 1, "window_tiles": 6,
-                 "link_bytes": (2 * 21 + sum(j0 * (6 - j0) for j0 in range(6))) * tile}
+                 "link_bytes": _moved(6, 1) * tile}
     # a roomy budget: four lanes, each holding the whole matrix in one pass
     p = eor.loglike_host_plan(333, 4, 1 << 30)
-    assert p["lanes"] == 4 and p["cols_per_pass"] == 6 and p["link_bytes"] == 2 * 21 * tile
+    assert p["lanes"] == 4 and p["cols_per_pass"] == 6 and p["link_bytes"] == 21 * tile  # A only
     # explicit lanes that do not fit, and arguments out of range
     L = eor.lib()
     assert L.eor_loglike_host_plan(333, 4, 14 * tile, 2, None, None, None, None) == eor.EOR_ERR_OOM

@@ -21,7 +21,8 @@ def _schedule(n, avail, bs=4, seed=0):
     for k in range(N):
         for i in range(k, N):
             Ah[col_off(k) + i - k] = S[i * bs:(i + 1) * bs, k * bs:(k + 1) * bs].copy()
-    Lh = [None] * ntile
+    Lh = [None] * ntile      # the host factor: only what later passes read is written back
+    done = [None] * ntile    # every finished tile, to check the factor
     cols = avail // N                      # full-height tile columns that fit (>= 2)
     J = min(N, cols - min(4, cols // 2))   # the window keeps min(4, half) of them
     capC, cap = J * N, avail - J * N
@@ -41,6 +42,7 @@ def _schedule(n, avail, bs=4, seed=0):
                 for r in range(rows0):
                     src = col_off(kk) + (j0 - kk) + r
                     assert col_off(kk) <= src < col_off(kk + 1)
+                    assert Lh[src] is not None, "a window reads a tile that was never written back"
                     Lw[k * rows0 + r] = Lh[src]
             for blk in range(nt):  # workgroup -> tile (i, j) as ooc_window_kernel maps it
                 b, j = blk, j0
@@ -69,11 +71,16 @@ def _schedule(n, avail, bs=4, seed=0):
                     assert i < N and loc(l) + (i - l) == loc(j + 1) + blk
                     C[loc(l) + i - l] = C[loc(l) + i - l] - C[loc(j) + i - j] @ C[loc(j) + l - j].conj().T
         for t in range(nt):
-            Lh[col_off(j0) + t] = C[t]
+            done[col_off(j0) + t] = C[t]
+        # write-back: rows j1 .. N-1 of the pass's columns, the only part later passes read
+        if j1 < N:
+            for j in range(j0, j1):
+                for r in range(j1 - j, N - j):
+                    Lh[col_off(j) + r] = C[col_off(j) - col_off(j0) + r]
     L = np.zeros((npad, npad), complex)
     for k in range(N):
         for i in range(k, N):
-            L[i * bs:(i + 1) * bs, k * bs:(k + 1) * bs] = Lh[col_off(k) + i - k]
+            L[i * bs:(i + 1) * bs, k * bs:(k + 1) * bs] = done[col_off(k) + i - k]
     return np.tril(L), np.linalg.cholesky(S)
 
 
