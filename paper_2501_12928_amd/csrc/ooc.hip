@@ -184,11 +184,11 @@ __global__ __launch_bounds__(256) void ooc_pass_kernel(double2 *__restrict__ C, 
 // sub-blocks so that few steps wait on a barrier:
 //  - Cholesky, right-looking over the four block columns: one wave factors
 //    the diagonal block (no barrier inside a wave: its LDS accesses run in
-//    program order), one thread per row solves the panel below it, and all
-//    threads apply the rank-16 update to the rest;
+//    program order), one thread per row solves the panel below it, and the
+//    rank-16 update of the rest runs on FP64 MFMA, one wave per 16 x 16 block;
 //  - inverse: the four diagonal blocks are inverted at once, one wave each,
-//    then the blocks below them, nearest the diagonal first:
-//    V_ij = -V_ii sum_{k=j..i-1} L_ik V_kj.
+//    then the blocks below them, nearest the diagonal first, one wave per
+//    block on FP64 MFMA: V_ij = -V_ii sum_{k=j..i-1} L_ik V_kj.
 constexpr int PT = 512;  // threads of the diagonal factorisation
 constexpr int PB = 16;   // sub-block size
 constexpr int NPB = OT / PB;
@@ -198,7 +198,6 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
                                                         int64_t j, OocState *st) {
     __shared__ double2 S[OT][OT + 1];              // C_jj, then L_jj (lower)
     __shared__ double2 V[OT][OT + 1];              // L_jj^-1 (lower; zero above)
-    __shared__ double2 X[NPB - 1][PB][PB + 1];     // block products of the inverse
     __shared__ double dinv[OT], lsq[OT];
     __shared__ double2 yj[OT];
     __shared__ int fail_col;
@@ -276,19 +275,30 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
                 for (int c = 0; c < PB; ++c) S[r][b0 + c] = x[c];
             }
             __syncthreads();
-            // rank-16 update of the rest: S[r][s] -= sum_t L[r][t] conj(L[s][t]), r0 <= s <= r
+            // rank-16 update of the rest, S[r][s] -= sum_t L[r][t] conj(L[s][t]), by
+            // 16 x 16 blocks (I, J), kb < J <= I, one wave each on FP64 MFMA (a
+            // diagonal block is updated whole: its upper part is never read)
+            {
+                int bi = 0, bj = 0, idx = 0;
+                for (int ii = kb + 1; ii < NPB; ++ii)
+                    for (int jj = kb + 1; jj <= ii; ++jj, ++idx)
+                        if (idx == wv) bi = ii, bj = jj;
+                if (wv < idx) {
+                    const int l16 = lane & 15, q = lane >> 4;
+                    d4 t1 = d4{0, 0, 0, 0}, t2 = d4{0, 0, 0, 0}, t3 = d4{0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < OT2 / PT; ++u) {
-                const int e = tid + PT * u, r = e >> 6, sc = e & 63;
-                if (sc >= r0 && sc <= r) {
-                    double2 acc = S[r][sc];
-#pragma unroll
-                    for (int t = 0; t < PB; ++t) {
-                        const double2 a = S[r][b0 + t], b = S[sc][b0 + t];
-                        acc.x -= a.x * b.x + a.y * b.y;
-                        acc.y -= a.y * b.x - a.x * b.y;
+                    for (int s0 = 0; s0 < PB; s0 += 4) {
+                        const double2 xv = S[PB * bi + l16][b0 + s0 + q];  // A[i][k]
+                        const double2 yv = S[PB * bj + l16][b0 + s0 + q];  // B[k][j] = conj(L[s][t]) parts
+                        t1 = mfma64(xv.x, yv.x, t1);
+                        t2 = mfma64(xv.y, yv.y, t2);
+                        t3 = mfma64(xv.x + xv.y, yv.x - yv.y, t3);
                     }
-                    S[r][sc] = acc;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        double2 &e = S[PB * bi + q + 4 * r][PB * bj + l16];
+                        e = make_double2(e.x - (t1[r] + t2[r]), e.y - (t3[r] - t1[r] + t2[r]));
+                    }
                 }
             }
             __syncthreads();
@@ -323,31 +333,34 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
         }
     }
     __syncthreads();
-    // blocks below the diagonal, distance dd = i - jb: X = sum_k L_ik V_k,jb, then V_i,jb = -V_ii X
+    // blocks below the diagonal, distance dd = ib - jb, one wave each on FP64
+    // MFMA: X = sum_k L_ib,k V_k,jb, then V_ib,jb = -V_ib,ib X, with X kept in
+    // the wave's accumulators (lane holds X[q + 4r][l16], which is the second
+    // operand of k-step r of the next product); complex products with three
+    // real ones: re = T1 - T2, im = T3 - T1 - T2
     for (int dd = 1; dd < NPB; ++dd) {
-        const int nblk = NPB - dd;
-        for (int e = tid; e < nblk * PB * PB; e += PT) {
-            const int jb = e >> 8, a = (e >> 4) & 15, b = e & 15, ib = jb + dd;
-            double sr = 0.0, si = 0.0;
-#pragma unroll 4
-            for (int k = PB * jb; k < PB * ib; ++k) {
-                const double2 l = S[PB * ib + a][k], v = V[k][PB * jb + b];
-                sr += l.x * v.x - l.y * v.y;
-                si += l.x * v.y + l.y * v.x;
+        if (wv < NPB - dd) {
+            const int jb = wv, ib = jb + dd, l16 = lane & 15, q = lane >> 4;
+            d4 t1 = d4{0, 0, 0, 0}, t2 = d4{0, 0, 0, 0}, t3 = d4{0, 0, 0, 0};
+            for (int k0 = PB * jb; k0 < PB * ib; k0 += 4) {
+                const double2 l = S[PB * ib + l16][k0 + q];  // A[i][k]
+                const double2 v = V[k0 + q][PB * jb + l16];  // B[k][j]
+                t1 = mfma64(l.x, v.x, t1);
+                t2 = mfma64(l.y, v.y, t2);
+                t3 = mfma64(l.x + l.y, v.x + v.y, t3);
             }
-            X[jb][a][b] = make_double2(sr, si);
-        }
-        __syncthreads();
-        for (int e = tid; e < nblk * PB * PB; e += PT) {
-            const int jb = e >> 8, a = (e >> 4) & 15, b = e & 15, ib = jb + dd;
-            double sr = 0.0, si = 0.0;
-#pragma unroll 4
-            for (int t = 0; t <= a; ++t) {
-                const double2 v = V[PB * ib + a][PB * ib + t], x = X[jb][t][b];
-                sr += v.x * x.x - v.y * x.y;
-                si += v.x * x.y + v.y * x.x;
+            const d4 xr = t1 - t2, xi = t3 - t1 - t2;
+            d4 u1 = d4{0, 0, 0, 0}, u2 = d4{0, 0, 0, 0}, u3 = d4{0, 0, 0, 0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double2 a = V[PB * ib + l16][PB * ib + 4 * r + q];  // V_ii (zero above its diagonal)
+                u1 = mfma64(a.x, xr[r], u1);
+                u2 = mfma64(a.y, xi[r], u2);
+                u3 = mfma64(a.x + a.y, xr[r] + xi[r], u3);
             }
-            V[PB * ib + a][PB * jb + b] = make_double2(-sr, -si);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                V[PB * ib + q + 4 * r][PB * jb + l16] = make_double2(-(u1[r] - u2[r]), -(u3[r] - u1[r] - u2[r]));
         }
         __syncthreads();
     }
