@@ -53,7 +53,6 @@ namespace {
 
 constexpr int A_COL_BYTES = TS * 16;  // one column of a storage tile of A
 constexpr int ALIGN_COLS = 64;        // panel columns between re-alignments of the workgroup's waves
-constexpr int TRI_SPLIT = 4;          // slices of threads that share each dot product of the triangular inverse
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -233,7 +232,6 @@ struct Shared {
     double2 ys[TS];                 // y_j
     double dg[TS];                  // pivots of the current diagonal tile
     double red[TS];                 // |y_j|^2 per row
-    double2 part[TRI_SPLIT * TS];   // partial sums of the triangular inverse, [p][row]
     int task_sh;
 };
 
@@ -387,41 +385,77 @@ __device__ inline void run_task(Shared &sh, double2 *L, double2 *yv, const InstD
                 __syncthreads();
 
                 // ---- in-place inverse of the lower-triangular L_jj -----
-                // Columns from the last to the first:
-                //   Linv[c][c] = 1 / L[c][c]
-                //   Linv[r][c] = -(sum_{k=c+1..r} Linv[r][k] L[k][c]) / L[c][c],  r > c
-                // Each sum is split over TRI_SPLIT slices of the threads (thread =
-                // row, slice p takes k = c+1+p, c+1+p+TRI_SPLIT, ...) and the
-                // partials are added in a fixed order, so the result does not
-                // depend on the launch shape.
-                for (int c = S - 1; c >= 0; --c) {
-                    const int r = tid % S, p = tid / S;
-                    if (p < TRI_SPLIT) {
-                        double sr = 0.0, si = 0.0;
-                        for (int k = c + 1 + p; k <= r; k += TRI_SPLIT) {
-                            const double2 x = sh.Dt[k * S + r];  // Linv[r][k] (already inverted)
-                            const double2 l = sh.Dt[c * S + k];  // L[k][c]
-                            sr += x.x * l.x - x.y * l.y;
-                            si += x.x * l.y + x.y * l.x;
-                        }
-                        sh.part[p * S + r] = make_double2(sr, si);
-                    }
-                    __syncthreads();
-                    if (tid < S) {
-                        const double lcc = sh.Dt[c * S + c].x;
-                        if (r > c) {
-                            double2 acc = sh.part[r];
-#pragma unroll
-                            for (int pp = 1; pp < TRI_SPLIT; ++pp) {
-                                acc.x += sh.part[pp * S + r].x;
-                                acc.y += sh.part[pp * S + r].y;
+                // Blocked on 16 x 16 blocks (NB of them per side). First every
+                // diagonal block is inverted in place, one wave each, row by
+                // row: Linv[r][c] = -(sum_{t=c..r-1} L[r][t] Linv[t][c]) / L[r][r]
+                // (a wave's LDS accesses run in program order, so each row reads
+                // L before the same row's results replace it). Then the block
+                // columns from the right: for jb = NB-2 .. 0, every block below
+                // the diagonal, Linv_ib,jb = -(sum_{k=jb+1..ib} Linv_ib,k L_k,jb)
+                // Linv_jb,jb, one wave each on FP64 MFMA; its first product is
+                // formed transposed, so that the accumulators are the first
+                // operand of the second. Results wait for a barrier before they
+                // replace the L blocks that other waves still read.
+                {
+                    constexpr int NB = S / 16;
+                    const int wv = uniform(tid >> 6), ln = tid & 63, l16 = ln & 15, q = ln >> 4;
+                    if (wv < NB && ln < 16) {
+                        const int b0 = 16 * wv, cc = ln;
+                        sh.Dt[(b0 + cc) * S + b0 + cc] = make_double2(1.0 / sqrt(sh.dg[b0 + cc]), 0.0);
+                        for (int r = 1; r < 16; ++r) {
+                            double sr = 0.0, si = 0.0;
+                            if (r > cc) {
+                                for (int t = cc; t < r; ++t) {
+                                    const double2 l = sh.Dt[(b0 + t) * S + b0 + r];   // L[r][t]
+                                    const double2 v = sh.Dt[(b0 + cc) * S + b0 + t];  // Linv[t][c]
+                                    sr += l.x * v.x - l.y * v.y;
+                                    si += l.x * v.y + l.y * v.x;
+                                }
+                                const double f = -1.0 / sqrt(sh.dg[b0 + r]);
+                                sh.Dt[(b0 + cc) * S + b0 + r] = make_double2(sr * f, si * f);
                             }
-                            sh.Dt[c * S + r] = make_double2(-acc.x / lcc, -acc.y / lcc);
-                        } else if (r == c) {
-                            sh.Dt[c * S + c] = make_double2(1.0 / lcc, 0.0);
                         }
                     }
                     __syncthreads();
+                    for (int jb = NB - 2; jb >= 0; --jb) {
+                        const int ib = jb + 1 + wv;
+                        const bool mine = uniform(ib < NB ? 1 : 0) != 0;
+                        d4 vr = d4{0, 0, 0, 0}, vi = d4{0, 0, 0, 0};
+                        if (mine) {
+                            // Y^T = sum_k L_k,jb^T Linv_ib,k^T: lane holds Y^T[q + 4r][l16]
+                            d4 t1 = d4{0, 0, 0, 0}, t2 = d4{0, 0, 0, 0}, t3 = d4{0, 0, 0, 0};
+                            for (int k = jb + 1; k <= ib; ++k) {
+#pragma unroll
+                                for (int s0 = 0; s0 < 16; s0 += 4) {
+                                    const double2 a = sh.Dt[(16 * jb + l16) * S + 16 * k + s0 + q];  // L[16k+s0+q][16jb+l16]
+                                    const double2 b = sh.Dt[(16 * k + s0 + q) * S + 16 * ib + l16];  // Linv[16ib+l16][16k+s0+q]
+                                    t1 = mfma64(a.x, b.x, t1);
+                                    t2 = mfma64(a.y, b.y, t2);
+                                    t3 = mfma64(a.x + a.y, b.x + b.y, t3);
+                                }
+                            }
+                            const d4 yr = t1 - t2, yi = t3 - t1 - t2;
+                            // Linv_ib,jb = -Y Linv_jb,jb: k-step r takes Y[l16][4r + q] = (yr[r], yi[r])
+                            d4 u1 = d4{0, 0, 0, 0}, u2 = d4{0, 0, 0, 0}, u3 = d4{0, 0, 0, 0};
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const double2 b = sh.Dt[(16 * jb + l16) * S + 16 * jb + 4 * r + q];  // Linv_jb,jb[4r+q][l16]
+                                u1 = mfma64(yr[r], b.x, u1);
+                                u2 = mfma64(yi[r], b.y, u2);
+                                u3 = mfma64(yr[r] + yi[r], b.x + b.y, u3);
+                            }
+                            vr = -(u1 - u2);
+                            vi = -(u3 - u1 - u2);
+                        }
+                        __syncthreads();
+                        if (mine) {
+                            // lane holds Linv_ib,jb[q + 4r][l16]
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                sh.Dt[(16 * jb + l16) * S + 16 * ib + q + 4 * r] = make_double2(vr[r], vi[r]);
+                        }
+                        __syncthreads();
+                    }
                 }
 
                 // ---- y_j = Linv w_j ---------------------------------------
