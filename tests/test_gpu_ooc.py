@@ -42,6 +42,27 @@ def test_ooc_matches_oracle_on_its_own_A(orc, budget):
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
 
 
+def test_ooc_shell_bins_and_scales(orc):
+    """Bins of unequal size (shell growth) and per-bin scales s_b, two lanes
+    with several passes (n = 450: 8 tile rows), against the oracle."""
+    import paper_2501_12928_amd as eor
+    inst = synth.small(seed=76, m=1000, n=450, n_k=6, n_eor=390, n_theta=7, shells=True)
+    inst.bin_scale = np.array([0.5, 2.0, 1.0, 3.0, 0.1, 7.0])
+    A, dbar, c, K0 = orc.precompute(inst.T, inst.noise_var, inst.d)
+    ref, rinfo = orc.loglike(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale, inst.theta)
+    assert np.all(rinfo == 0)
+    N = 8
+    budget = 2 * ((6 * N + 2) * TILE_BYTES + 4 * N * 64 * 16 + 8192)
+    plan = eor.loglike_host_plan(inst.n, inst.n_k, budget, 2)
+    assert plan["lanes"] == 2 and 1 < plan["cols_per_pass"] < N
+    print(f"gpu: out-of-core shells and scales n=450 plan {plan}", flush=True)
+    got, info = eor.loglike_host(A, dbar, c, K0, inst.n_k, inst.bin_of, inst.fixed_var, inst.bin_scale,
+                                 inst.theta, budget, lanes=2)
+    assert np.all(info == 0)
+    assert np.all(np.abs(got - ref) <= tol(ref))
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
+
+
 def test_ooc_lanes_give_the_same_bits(orc):
     """With a budget that holds the whole matrix in one pass whatever the lane
     count, every theta runs the same kernels in the same order on its lane:
