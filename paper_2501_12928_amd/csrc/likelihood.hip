@@ -10,7 +10,8 @@
 //   for each tile column j:
 //     diagonal:  D = A_jj + diag(Phi^{-1}) - sum_{k<j} L_jk L_jk^H (MFMA) -> LDS;
 //                Cholesky of D in LDS; in-place triangular inverse
-//                Linv = L_jj^{-1} (kept in LDS); y_j = Linv w_j
+//                Linv = L_jj^{-1} (kept in LDS; blocked on 16 x 16 blocks, the
+//                blocks below its diagonal on MFMA); y_j = Linv w_j
 //     below:     for i > j: X = A_ij - sum_{k<j} L_ik L_jk^H (MFMA)
 //                           L_ij = X Linv^H (MFMA, operand from LDS)
 //                           w_i -= L_ij y_j
