@@ -45,6 +45,17 @@ __device__ inline d4 mfma64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Orders one wave's LDS accesses across its lanes. The hardware performs a
+// wave's LDS instructions in program order; the wave-scope release, wave
+// barrier and acquire keep the compiler from moving a lane's load of a value
+// that another lane stores (or a store that another lane's load must precede)
+// across this point. No instruction is emitted for it.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct OocState {
     double logdet;    // 2 sum ln L_dd
     double quad;      // |y|^2
@@ -183,8 +194,9 @@ __global__ __launch_bounds__(256) void ooc_pass_kernel(double2 *__restrict__ C, 
 // and y_j = L_jj^-1 w_j. One workgroup of PT threads, blocked on 16 x 16
 // sub-blocks so that few steps wait on a barrier:
 //  - Cholesky, right-looking over the four block columns: one wave factors
-//    the diagonal block (no barrier inside a wave: its LDS accesses run in
-//    program order), one thread per row solves the panel below it, and the
+//    the diagonal block (no workgroup barrier: a wave's LDS accesses run in
+//    program order, and wave_sync keeps the compiler to it), one thread per
+//    row solves the panel below it, and the
 //    rank-16 update of the rest runs on FP64 MFMA, one wave per 16 x 16 block;
 //  - inverse: the four diagonal blocks are inverted at once, one wave each,
 //    then the blocks below them, nearest the diagonal first, one wave per
@@ -236,6 +248,7 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
                     S[b0 + br][b0 + c] = make_double2(x.x * il, x.y * il);
                 }
                 if (lane == 0) S[b0 + c][b0 + c] = make_double2(l, 0.0);
+                wave_sync();  // the scaled column c, stored by lanes bs = 0, is read by every lane
                 if (br > c) {
                     const double2 a = S[b0 + br][b0 + c];
 #pragma unroll
@@ -250,6 +263,7 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
                         }
                     }
                 }
+                wave_sync();  // column c + 1 and its pivot, updated by other lanes, are read next
             }
         }
         __syncthreads();
