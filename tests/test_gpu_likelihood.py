@@ -453,6 +453,55 @@ def test_largest_shape_block_rotation():
     assert np.all(np.abs(lb - ref) <= tol(ref)), np.max(np.abs(lb - ref))
 
 
+def test_n16384_four_block_rotation():
+    """n = 16384 (256 tiles per side; each theta's factor is 4.3 GB, so its
+    byte offsets pass 2^32), by the same property with four blocks: four
+    independent 4096-coefficient problems with the same bins, stacked
+    block-diagonally and mixed four columns at a time (coefficient j of each
+    block by a random 4 x 4 unitary; all four have the same prior variance),
+    must give the sum of the four logL, at a random theta and at the two
+    corners of the prior box. Each 4096-coefficient problem is of the size
+    held to the oracle elsewhere."""
+    rng = np.random.default_rng(16384)
+    n1, m1, n_k, n_eor, nb = 4096, 4400, 6, 3584, 4
+    parts = [synth.make_instance(rng, m=m1, n=n1, n_k=n_k, n_eor=n_eor, n_theta=1, lo=-1.0, hi=3.0)
+             for _ in range(nb)]
+    for p in parts[1:]:
+        assert np.array_equal(p.bin_of, parts[0].bin_of)
+        assert np.array_equal(p.fixed_var, parts[0].fixed_var)
+        assert np.array_equal(p.bin_scale, parts[0].bin_scale)
+    theta = np.ascontiguousarray(np.stack([parts[0].theta[0], np.full(n_k, -1.0), np.full(n_k, 3.0)]))
+    # U[j] (4 x 4 unitary per coefficient): Q of a complex Gaussian matrix
+    g = rng.standard_normal((n1, nb, nb)) + 1j * rng.standard_normal((n1, nb, nb))
+    U = np.linalg.qr(g)[0]
+    assert np.allclose(np.einsum("jrc,jrd->jcd", U.conj(), U), np.eye(nb)[None], atol=1e-12)
+    n, m = nb * n1, nb * m1
+    # T' = blockdiag(T_0 .. T_3) U: block (r, c) is T_r scaled column-wise by U[:, r, c]
+    T = np.empty((m, n), dtype=np.complex128)
+    for r, p in enumerate(parts):
+        for c in range(nb):
+            T[r * m1:(r + 1) * m1, c * n1:(c + 1) * n1] = p.T * U[None, :, r, c]
+    big = synth.Instance(T=T, noise_var=np.concatenate([p.noise_var for p in parts]),
+                         d=np.concatenate([p.d for p in parts]), n_k=n_k,
+                         bin_of=np.concatenate([p.bin_of for p in parts]),
+                         fixed_var=np.concatenate([p.fixed_var for p in parts]),
+                         bin_scale=parts[0].bin_scale, theta=theta, theta_true=parts[0].theta_true,
+                         lo=parts[0].lo, hi=parts[0].hi)
+    del T
+    _say("gpu: four n=4096 blocks, 3 theta")
+    ref = np.zeros(len(theta))
+    for p in parts:
+        lp, ip = run_instance(p, theta=theta)
+        assert np.all(ip == 0)
+        ref += lp
+    _say("gpu: n=16384 mixed, 3 theta (one theta per CU)")
+    lb, ib = run_instance(big)
+    assert np.all(ib == 0)
+    err = np.abs(lb - ref)
+    _say(f"n=16384: max |dlogL| {err.max():.3e}, relative {np.max(err / np.abs(ref)):.3e}")
+    assert np.all(err <= tol(ref)), err.max()
+
+
 def test_fp64_mfma_probe():
     """The measured FP64 matrix peak is positive and below the part's
     specification (78.6 TFLOP/s at 2.4 GHz); bad arguments are refused."""
