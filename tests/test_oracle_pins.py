@@ -145,6 +145,36 @@ def test_invariants(orc):
     np.testing.assert_allclose(r4, r4k, rtol=1e-12)
 
 
+def test_independent_blocks_add_under_mixing(orc):
+    """(I6) Four independent problems with the same bins, stacked
+    block-diagonally (data rows and noise concatenated) and mixed coefficient
+    by coefficient with a random 4 x 4 unitary across the blocks: every mixed
+    coefficient has the same prior variance, so the data covariance and the
+    logL are those of the four problems side by side, the sum of their logL.
+    The same construction checks the GPU path at sizes the oracle cannot
+    reach; a block of T scaled by 1.01 must break it."""
+    rng = np.random.default_rng(16384)
+    n1, m1, n_k, n_eor, nb = 48, 70, 3, 40, 4
+    parts = [synth.make_instance(rng, m=m1, n=n1, n_k=n_k, n_eor=n_eor, n_theta=1, lo=-1.0, hi=3.0)
+             for _ in range(nb)]
+    theta = np.ascontiguousarray(np.stack([parts[0].theta[0], np.full(n_k, -1.0), np.full(n_k, 3.0)]))
+    U = np.stack([_unitary(rng, nb) for _ in range(n1)])
+    T = np.empty((nb * m1, nb * n1), dtype=np.complex128)
+    for r, p in enumerate(parts):
+        for c in range(nb):
+            T[r * m1:(r + 1) * m1, c * n1:(c + 1) * n1] = p.T * U[None, :, r, c]
+    noise = np.concatenate([p.noise_var for p in parts])
+    d = np.concatenate([p.d for p in parts])
+    bins = np.concatenate([p.bin_of for p in parts])
+    fixed = np.concatenate([p.fixed_var for p in parts])
+    ref = sum(orc.loglike_instance(p, theta=theta)[0] for p in parts)
+    got, _ = orc.loglike(*orc.precompute(T, noise, d), n_k, bins, fixed, None, theta)
+    np.testing.assert_allclose(got, ref, rtol=1e-11)
+    T[:m1, :n1] *= 1.01
+    bad, _ = orc.loglike(*orc.precompute(T, noise, d), n_k, bins, fixed, None, theta)
+    assert np.all(np.abs(bad - ref) > 1e-3)
+
+
 def test_batch_position_independent(orc):
     """(I5) logL[b] does not depend on B or the order of the batch."""
     inst = synth.small(seed=9, m=50, n=30, n_k=4, n_theta=12)
