@@ -3,8 +3,6 @@ varies (eor_surrogate_gate): the same means, spreads, member outputs and
 decisions, on two calls in a row (the second smaller, so it runs on what the
 first left in the fixed scratch), through the C ABI; a batch beyond the
 scratch is refused before any launch."""
-import ctypes
-
 import numpy as np
 import pytest
 
