@@ -31,7 +31,7 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix)
 CONFIG_ID = 3               # 20000 x 4096, 12 bins, B = 512
-KERNEL_SRC = os.path.join(ROOT, "paper_2501_12928_amd", "csrc", "likelihood.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2501_12928_amd", "csrc", f) for f in ("likelihood.hip", "common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "likelihood_n4096_B512_traffic.json")
 
 
@@ -42,13 +42,17 @@ def flops_per_theta(n: int) -> float:
 
 
 def kernel_digest() -> str:
-    """Hash of the likelihood kernel's code with comments and blank space
-    removed: counters taken on a build stay valid across comment edits."""
-    src = open(KERNEL_SRC).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    src = re.sub(r"//[^\n]*", "", src)
-    src = "\n".join(ln.strip() for ln in src.splitlines() if ln.strip())
-    return hashlib.sha256(src.encode()).hexdigest()[:16]
+    """Hash of the likelihood kernel's code (its source and the header it
+    includes) with comments and blank space removed: counters taken on a
+    build stay valid across comment edits, and only then."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        src = open(path).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(ln.strip() for ln in src.splitlines() if ln.strip()).encode())
+        h.update(b"\0")
+    return h.hexdigest()[:16]
 
 
 def counters_per_launch():
