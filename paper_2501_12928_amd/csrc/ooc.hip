@@ -149,7 +149,7 @@ __device__ inline void tile_sub(double2 *__restrict__ Ct, int w, int l16, int q,
 // tiles, rows j .. N-1, from local tile col_off(j) - col_off(j0)). One
 // workgroup per tile (i, j): C_ij -= sum_k L_ik L_jk^H over the window of
 // earlier columns, window column k holding rows j0 .. N-1 (N - j0 tiles).
-__global__ __launch_bounds__(256) void ooc_window_kernel(double2 *__restrict__ C, const double2 *__restrict__ Lw,
+__global__ __launch_bounds__(256, 2) void ooc_window_kernel(double2 *__restrict__ C, const double2 *__restrict__ Lw,
                                                          int W, int64_t j0, int64_t j1, int64_t N,
                                                          const OocState *st) {
     if (st->info != 0) return;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void ooc_window_kernel(double2 *__restrict__ C
 // After column k of a pass is factored: C_ij -= L_ik L_jk^H for every later
 // column j < j1 of the pass and i >= j, one workgroup per tile (the tiles of
 // columns k+1 .. j1-1 are one contiguous run of the pass's packing).
-__global__ __launch_bounds__(256) void ooc_pass_kernel(double2 *__restrict__ C, int64_t k, int64_t j0, int64_t j1,
+__global__ __launch_bounds__(256, 2) void ooc_pass_kernel(double2 *__restrict__ C, int64_t k, int64_t j0, int64_t j1,
                                                        int64_t N, const OocState *st) {
     if (st->info != 0) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, l16 = lane & 15, q = lane >> 4;
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(PT) void ooc_potrf_kernel(double2 *__restrict__ C0,
 
 // L_ij = C_i Linv^H for the tiles below the diagonal (t = blockIdx.x + 1),
 // then w_i -= L_ij y_j.
-__global__ __launch_bounds__(256) void ooc_trsm_kernel(double2 *__restrict__ C, const double2 *__restrict__ Linv,
+__global__ __launch_bounds__(256, 2) void ooc_trsm_kernel(double2 *__restrict__ C, const double2 *__restrict__ Linv,
                                                        double2 *__restrict__ w, const double2 *__restrict__ y,
                                                        int64_t j, const OocState *st) {
     if (st->info != 0) return;
