@@ -318,25 +318,23 @@ __global__ __launch_bounds__(256) void herk_bf16_kernel(const unsigned short *__
     const int64_t plane = n_pad * m_pad;
     // the thread's share of a step: 16 bytes (8 rows) of one column of one
     // plane of one panel; e = ((panel * NP + p) * 64 + col) * 4 + 8-row group
-    const unsigned short *src[BF_LOADS];
-    int dst[BF_LOADS];
-#pragma unroll
-    for (int u = 0; u < BF_LOADS; ++u) {
-        const int e = tid + 256 * u;
-        const int g8 = e & 3, col = (e >> 2) & 63, pp = e >> 8;  // pp = panel * NP + plane
-        const int panel = pp / NP, p = pp % NP;
-        const int64_t gcol = TS * (panel == 0 ? ti : tj) + col;
-        src[u] = P + (int64_t)p * plane + gcol * m_pad + 8 * g8;
-        dst[u] = panel * BF_PANEL + (p * 64 + col) * BF_COL + 8 * g8;
-    }
+    // = tid + 256 u, so read u is plane u % NP of panel u / NP, at the
+    // thread's own column and row group. Two column bases per thread and
+    // offsets that are uniform per read (the plane), rather than a pointer
+    // and an LDS offset per read: fewer registers live through the loop.
+    const int g8 = tid & 3, col = (tid >> 2) & 63;
+    const unsigned short *base[2] = {P + (TS * ti + col) * m_pad + 8 * g8, P + (TS * tj + col) * m_pad + 8 * g8};
+    const int dthr = col * BF_COL + 8 * g8;
     s8v pre[BF_LOADS];
     auto fetch = [&](int64_t s0) {
 #pragma unroll
-        for (int u = 0; u < BF_LOADS; ++u) pre[u] = *reinterpret_cast<const s8v *>(src[u] + s0);
+        for (int u = 0; u < BF_LOADS; ++u)
+            pre[u] = *reinterpret_cast<const s8v *>(base[u / NP] + (int64_t)(u % NP) * plane + s0);
     };
     auto stash = [&](int b) {
 #pragma unroll
-        for (int u = 0; u < BF_LOADS; ++u) *reinterpret_cast<s8v *>(&lds[b][dst[u]]) = pre[u];
+        for (int u = 0; u < BF_LOADS; ++u)
+            *reinterpret_cast<s8v *>(&lds[b][(u / NP) * BF_PANEL + (u % NP) * 64 * BF_COL + dthr]) = pre[u];
     };
     // B operand a = W[s][64 ti + 16 w + l16] (panel 0), A operands b = W[s][64 tj + 16 cb + l16] (panel 1)
     auto opnd = [&](int b, int panel, int p, int col) {
