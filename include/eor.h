@@ -476,9 +476,9 @@ eor_status eor_loglike_host_plan(int64_t n, int32_t n_k, size_t device_bytes, in
  * (the sky modes) and c n_freq n_bl n_uv complex (partial sums of the pixel
  * sum over c <= 16 chunks of the pixels, added in chunk order).
  * Errors: EOR_ERR_ARG (sizes < 1, n_freq > 65535, n_bl > 65535 x 32, n_uv > 65535 x 64,
- * n_eta > 2^20, n_pix n_uv > 2^34, more than 2^31 - 1 tiles of 32 baselines
- * x 128 uv cells x pixel chunks, NULL array, ldT too small, norm not
- * finite), EOR_ERR_HIP, EOR_ERR_OOM.
+ * n_eta > 2^20, n_pix n_uv > 2^34, n_freq n_bl n_uv > 2^40, more than
+ * 2^31 - 1 tiles of 32 baselines x 128 uv cells x pixel chunks, NULL array,
+ * ldT too small, norm not finite), EOR_ERR_HIP, EOR_ERR_OOM.
  */
 eor_status eor_forward_model(int64_t n_freq, int64_t n_bl, int64_t n_pix, int64_t n_uv, int64_t n_eta,
                              const double *freq, const double *bl, const double *lm, const double *beam,

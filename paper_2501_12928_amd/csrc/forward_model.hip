@@ -273,6 +273,8 @@ extern "C" eor_status eor_forward_model(int64_t n_freq, int64_t n_bl, int64_t n_
     const int64_t units = base * n_chunk, rows = n_freq * n_bl;
     if (units > (int64_t)INT32_MAX)
         return eor::fail_status(EOR_ERR_ARG, "eor_forward_model: more than 2^31 - 1 tiles");
+    if (rows * n_uv > ((int64_t)1 << 40))  // keeps the partials' byte count far from overflow
+        return eor::fail_status(EOR_ERR_ARG, "eor_forward_model: n_freq n_bl n_uv > 2^40");
     hipStream_t hs = (hipStream_t)stream;
     double2 *S = nullptr, *G = nullptr;
     hipError_t e = hipMallocAsync((void **)&S, (size_t)n_pix * n_uv * sizeof(double2), hs);

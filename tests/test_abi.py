@@ -52,6 +52,10 @@ def test_argument_errors_without_gpu():
     assert L.eor_forward_model(1, 1, 1, 2, 2, p, p, p, p, p, p, 1.0, p, 3, None) == eor.EOR_ERR_ARG
     assert L.eor_forward_model(1, 1, 1, 1, 1, p, None, p, p, p, p, 1.0, p, 1, None) == eor.EOR_ERR_ARG
     assert L.eor_forward_model(1, 1, 1, 1, 1, p, p, p, p, p, p, float("inf"), p, 1, None) == eor.EOR_ERR_ARG
+    # every size within its own limit and under 2^31 tiles, but 2^20 x 4194240 entries of G
+    assert L.eor_forward_model(1, 1 << 20, 1, 65535 * 64, 1, p, p, p, p, p, p, 1.0, p, 65535 * 64,
+                               None) == eor.EOR_ERR_ARG
+    assert b"2^40" in L.eor_last_error()
     # out-of-core likelihood: sizes, bin map, fixed variances and the device budget are checked first
     A = np.zeros((4, 4), dtype=np.complex128)
     db = np.zeros(4, dtype=np.complex128)
