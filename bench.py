@@ -484,6 +484,40 @@ def bench_instrument(args):
     ctx.close()
 
 
+def link_probe(mib: int = 512, reps: int = 5):
+    """Pinned host <-> device copy rates on this machine (GB/s): one direction at
+    a time, then both at once on two streams. The reference for how much of
+    the host link the out-of-core schedule uses."""
+    import torch
+    n = mib << 20
+    h = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    h2 = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(n, dtype=torch.uint8, device="cuda")
+    d2 = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return nbytes * reps / (time.perf_counter() - t0) / 1e9
+
+    def both():
+        with torch.cuda.stream(s1):
+            d.copy_(h, non_blocking=True)
+        with torch.cuda.stream(s2):
+            h2.copy_(d2, non_blocking=True)
+
+    out = {"h2d_gbs": rate(lambda: d.copy_(h, non_blocking=True), n),
+           "d2h_gbs": rate(lambda: h.copy_(d, non_blocking=True), n),
+           "both_directions_gbs": rate(both, 2 * n), "bytes_per_copy": n}
+    del h, h2, d, d2
+    return out
+
+
 def bench_ooc(args):
     """Out-of-core likelihood at 20000 x 4096 (12 bins): A exported to host
     memory, then eor_loglike_host with the device limited to a window of
@@ -491,7 +525,8 @@ def bench_ooc(args):
     `--ooc-lanes` at a time (0 = the library's choice). Reports evals/s over
     the whole call (packing A into pinned memory included), the time of a
     one-theta call, the library's schedule (lanes, pass width, host<->device
-    bytes per theta) and the algorithmic FP64 rate, beside the in-core batch."""
+    bytes per theta) and the algorithmic FP64 rate, beside the in-core batch
+    and the box's raw pinned copy rates."""
     import torch
     import synth
     import paper_2501_12928_amd as eor
@@ -539,6 +574,7 @@ def bench_ooc(args):
         "host_device_bytes_per_theta": moved, "host_device_gbs": moved * B / t_ooc / 1e9,
         "tflops": B * flops_per_theta(n) / t_ooc / 1e12,
         "in_core_evals_per_s": B / t_in,
+        "link_probe": link_probe(),
         "info_nonzero": int((info != 0).sum()),
         "max_rel_diff_vs_in_core": float(np.max(np.abs(L - Lin) / np.abs(Lin)))}))
 
